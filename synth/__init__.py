@@ -1,0 +1,16 @@
+"""Seeded synthetic LQ optimal-control problems.
+
+This module only draws input data (dynamics, costs, initial states) from
+seeded random-number streams.  It contains none of the solver's arithmetic
+and is shared by the CPU oracle, the tests and the benchmark.
+"""
+from .problems import (  # noqa: F401
+    LQProblem,
+    SEED_ROOT,
+    config_sizes,
+    make_batch,
+    make_instance,
+    make_ragged,
+    random_problem,
+    stack,
+)

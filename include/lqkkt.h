@@ -1,0 +1,178 @@
+/*
+ * lqkkt.h -- batched factorised-Riccati solver for the KKT systems of
+ * equality-constrained, time-varying LQ optimal-control problems on gfx950.
+ *
+ * Problem (paper, Sec. "Problem statement and notation", eq. ocp-eq, E_j = I):
+ *   minimise  sum_{k<N} 1/2 [u_k;x_k]^T [[R_k, S_k],[S_k^T, Q_k]] [u_k;x_k] + [u_k;x_k]^T [r_k;q_k]
+ *             + 1/2 x_N^T Q_N x_N + q_N^T x_N
+ *   s.t.      x_0 = x_init,  x_{k+1} = A_k x_k + B_k u_k + f_k   (0 <= k < N)
+ * Solved: its KKT conditions after elimination of x_0 (eq. opt-cond-ocp-eq), unknowns
+ * u_0..u_{N-1}, x_1..x_N and the multipliers lam_0..lam_{N-1} of the dynamics, with the
+ * paper's sign convention (the x_k rows read S_k^T u_k + Q_k x_k + A_k^T lam_k - lam_{k-1} = -q_k).
+ *
+ * Method: the factorised Riccati recursion, i.e. the paper's block-column factorisation
+ * (Alg. "factor-block-column-riccati") with a single interval, which reduces to the
+ * stage-wise potrf / trmm / syrk sweep: chol([[R_k,S_k],[S_k^T,Q_k]] + V_k V_k^T) with
+ * V_k = [B_k^T; A_k^T] L^Q_{k+1}, giving L^R_k, L^S_k and the cost-to-go factor L^Q_k
+ * (P_k = L^Q_k L^Q_k^T, eq. riccati-recursion-P); the redundant factorisation
+ * (eq. redundant-fact) means only these lower factors are stored.
+ *
+ * ---------------------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ *
+ * Pointers.  Every array pointer is a DEVICE pointer (hipMalloc / torch CUDA tensors),
+ *   owned by the caller; the library never frees or retains them.  Host pointers are named
+ *   as such.  All compute calls are asynchronous on the caller's `stream`.
+ *
+ * Data layout (float64, row-major).  Instance i with horizon N_i, state size nx_i and input
+ *   size nu_i owns one contiguous block in each array, the blocks of instances 0..B-1 packed
+ *   back to back in order.  Block sizes (elements):
+ *     A  N nx nx   (A_k, k = 0..N-1)          B  N nx nu     R  N nu nu    S  N nu nx
+ *     Q  (N+1) nx nx (Q_k, k = 0..N)          q  (N+1) nx    r  N nu       f  N nx
+ *     x0 nx
+ *   Outputs:  x  N nx (x_k, k = 1..N)   u  N nu (u_k, k = 0..N-1)   lam  N nx (lam_k, k = 0..N-1)
+ *   Q_0 and q_0 multiply the fixed x_0 and are never read.  S and f may be NULL (zero).
+ *   Q_k and R_k enter through their symmetric parts 1/2 (M + M^T).
+ *   lq_plan_offsets() returns the element offset of each instance's block.
+ *
+ * Status.  The return value reports synchronous argument validation and launch status
+ *   only (LQ_OK, LQ_EINVAL, LQ_EUNSUPPORTED, LQ_EHIP, LQ_ENOMEM); lq_last_error() gives a
+ *   message for the calling thread.  Numerical outcomes are per instance in the device
+ *   array `info` (int32, length B):
+ *     0            success
+ *     k+1 > 0      the stage matrix of stage k was not positive definite (potrf convention);
+ *                  the factorisation of that instance continued with a unit pivot
+ *     LQ_INFO_NONFINITE (-1)      a non-finite value appeared in the instance's solution
+ *     LQ_INFO_NOT_CONVERGED (-2)  refinement stopped at max_it above tol (rel_res holds the
+ *                                 value reached)
+ *   lq_factor writes info; lq_solve keeps a positive (factor) code and otherwise overwrites.
+ */
+#ifndef LQKKT_H
+#define LQKKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LQ_OK 0
+#define LQ_EINVAL (-1)       /* invalid argument (null required pointer, non-positive size, ...) */
+#define LQ_EUNSUPPORTED (-2) /* sizes or mode outside what the built kernels handle             */
+#define LQ_EHIP (-3)         /* a HIP runtime call or kernel launch failed                       */
+#define LQ_ENOMEM (-4)       /* plan creation could not allocate its descriptor table           */
+
+#define LQ_INFO_OK 0
+#define LQ_INFO_NONFINITE (-1)
+#define LQ_INFO_NOT_CONVERGED (-2)
+
+/* Arithmetic of the factorisation.
+ *   LQ_F64        every step in float64; factors stored in float64.
+ *   LQ_MIXED_F32  stage products (trmm, syrk) in float32 with float32 accumulation, the stage
+ *                 Cholesky in float64, factors stored in float32; lq_solve refines in float64
+ *                 (float64 KKT residual, float64 correction sweeps) to opts->tol.
+ *   LQ_MIXED_BF16 as LQ_MIXED_F32 with the stage products on bf16 matrix cores (float32
+ *                 accumulation); for large nx.                                             */
+typedef enum { LQ_F64 = 0, LQ_MIXED_F32 = 1, LQ_MIXED_BF16 = 2 } lq_mode;
+
+/* Which packed array an offset query refers to. */
+typedef enum {
+  LQ_ARR_A = 0, LQ_ARR_B, LQ_ARR_Q, LQ_ARR_R, LQ_ARR_S, LQ_ARR_q, LQ_ARR_r, LQ_ARR_f, LQ_ARR_x0,
+  LQ_ARR_x, LQ_ARR_u, LQ_ARR_lam, LQ_ARR_COUNT
+} lq_array;
+
+/* Device pointers to the problem data of the whole batch (layout above). */
+typedef struct {
+  const double* A;
+  const double* B;
+  const double* Q;
+  const double* R;
+  const double* S;  /* may be NULL: S_k = 0 */
+  const double* q;
+  const double* r;
+  const double* f;  /* may be NULL: f_k = 0 */
+  const double* x0;
+} lq_data;
+
+/* Options of lq_solve / lq_solve_backward. */
+typedef struct {
+  double tol;      /* target for rel_res = ||b - K z||_inf / ||b||_inf (e.g. 1e-10)              */
+  int32_t max_it;  /* maximum refinement iterations (>= 0); in LQ_F64 mode 0 is usual            */
+  int32_t check;   /* 1: compute the float64 KKT residual of the final iterate into rel_res      */
+} lq_solve_opts;
+
+/* Opaque plan: sizes of every instance, precision, kernel variant, descriptor table. */
+typedef struct lq_plan lq_plan;
+
+/* Create a plan for `batch` instances.
+ *   N, nx, nu: HOST arrays of length batch (uniform batches pass arrays of equal values).
+ *   ckpt_stride: 0 stores the factors of every stage; s > 0 keeps only every s-th cost-to-go
+ *   factor and recomputes the others in lq_solve / lq_solve_backward (memory checkpointing).
+ * Allocates one small device descriptor table on the current device (freed by
+ * lq_plan_destroy); no other call allocates device memory.  Returns LQ_OK and *out. */
+int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx, const int32_t* nu,
+                   lq_mode mode, int32_t ckpt_stride, lq_plan** out);
+void lq_plan_destroy(lq_plan* plan);
+
+/* Bytes of device workspace the caller provides to lq_factor / lq_solve / lq_solve_backward
+ * (holds the factors, the backward-sweep vectors and refinement state).  256-byte aligned
+ * pointers are required. */
+size_t lq_plan_workspace_bytes(const lq_plan* plan);
+
+/* Total elements of the packed array `which` over the batch, and (if offsets_host is not
+ * NULL) the element offset of each instance's block into offsets_host[batch]. */
+int64_t lq_plan_offsets(const lq_plan* plan, lq_array which, int64_t* offsets_host);
+
+/* Name of the kernel variant the plan dispatches to (static string). */
+const char* lq_plan_variant(const lq_plan* plan);
+
+/* Factor sweep (backward in time): for k = N-1..0 the stage products and the stage
+ * Cholesky, storing L^R_k, L^S_k, L^Q_k in `workspace`; also the backward sweep of the
+ * right-hand side (q, r, f) that lq_solve continues.  `info` (device, int32[B]) receives the
+ * per-instance factor status.  lq_solve must be called with the same `data`. */
+int lq_factor(const lq_plan* plan, const lq_data* data, void* workspace, int32_t* info,
+              hipStream_t stream);
+
+/* Forward rollout u_k = -L^R_k^{-T}(L^S_k^T x_k + rbar_k), x_{k+1} = A_k x_k + B_k u_k + f_k,
+ * lam_k = L^Q_{k+1} L^Q_{k+1}^T x_{k+1} + p_{k+1}, then float64 iterative refinement
+ * (residual of eq. opt-cond-ocp-eq, correction solve with the stored factors) until
+ * rel_res <= opts->tol or opts->max_it iterations.  x, u, lam: device float64 outputs.
+ * rel_res: device float64[B] (may be NULL when opts->check == 0 and max_it == 0).
+ * iters: device int32[B] refinement iterations taken (may be NULL).
+ * info: device int32[B], read and updated. */
+int lq_solve(const lq_plan* plan, const lq_data* data, void* workspace, const lq_solve_opts* opts,
+             double* x, double* u, double* lam, double* rel_res, int32_t* iters, int32_t* info,
+             hipStream_t stream);
+
+/* Adjoint of lq_solve.  Given the solution (x, u, lam) from lq_solve with the same plan,
+ * data and factored workspace, and upstream gradients gx = dl/dx_k (k = 1..N, layout of x)
+ * and gu = dl/du_k (layout of u), solves K zbar = (gu, gx, 0) with the stored factors (K is
+ * symmetric), refined like lq_solve, and writes
+ *   gA_k = -(lambar_k x_k^T + lam_k xbar_k^T)      gB_k = -(lambar_k u_k^T + lam_k ubar_k^T)
+ *   gQ_k = -sym(xbar_k x_k^T) (k >= 1, gQ_0 = 0)   gR_k = -sym(ubar_k u_k^T)
+ *   gS_k = -(ubar_k x_k^T + u_k xbar_k^T)          gq_k = -xbar_k (gq_0 = 0), gr_k = -ubar_k
+ *   gf_k = -lambar_k                               gx0 = -(A_0^T lambar_0 + S_0^T ubar_0)
+ * with x_0 = x_init and xbar_0 = 0 (sym(M) = (M + M^T)/2, since Q and R enter through their
+ * symmetric parts).  Gradient arrays use the input layouts; gS and gf may be NULL.
+ * rel_res / iters / info as in lq_solve, for the adjoint system. */
+int lq_solve_backward(const lq_plan* plan, const lq_data* data, void* workspace,
+                      const lq_solve_opts* opts, const double* x, const double* u,
+                      const double* lam, const double* gx, const double* gu, double* gA,
+                      double* gB, double* gQ, double* gR, double* gS, double* gq, double* gr,
+                      double* gf, double* gx0, double* rel_res, int32_t* iters, int32_t* info,
+                      hipStream_t stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lq_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int lq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQKKT_H */

@@ -1,0 +1,159 @@
+"""Python binding of liblqkkt: marshals torch CUDA tensors and streams into the C ABI.
+
+Every numerical step runs in the library's HIP kernels; this module only packs arguments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence, Union
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import ARRAYS, LqData, LqSolveOpts, MODES, check
+
+INPUTS = ["A", "B", "Q", "R", "S", "q", "r", "f", "x0"]
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("lqkkt expects device tensors")
+    if t.dtype != torch.float64 and t.dtype != torch.int32 and t.dtype != torch.uint8:
+        raise ValueError(f"unexpected dtype {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("lqkkt expects contiguous tensors")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Plan:
+    """Sizes, precision and kernel variant of a batch; owns the device descriptor table."""
+
+    def __init__(self, N: Union[int, Sequence[int]], nx: Union[int, Sequence[int]],
+                 nu: Union[int, Sequence[int]], batch: Optional[int] = None, mode: str = "f64",
+                 ckpt_stride: int = 0):
+        lib = _lib.load()
+        if np.isscalar(N):
+            if batch is None:
+                raise ValueError("batch is required with scalar sizes")
+            Ns = np.full(batch, N, np.int32)
+            nxs = np.full(batch, nx, np.int32)
+            nus = np.full(batch, nu, np.int32)
+        else:
+            Ns, nxs, nus = (np.ascontiguousarray(a, dtype=np.int32) for a in (N, nx, nu))
+        self.batch = int(len(Ns))
+        self.N, self.nx, self.nu = Ns, nxs, nus
+        self.mode = mode
+        self._h = C.c_void_p()
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+        check(lib.lq_plan_create(self.batch, ip(Ns), ip(nxs), ip(nus), MODES[mode], int(ckpt_stride),
+                                 C.byref(self._h)), "lq_plan_create")
+        self.workspace_bytes = int(lib.lq_plan_workspace_bytes(self._h))
+        self.variant = lib.lq_plan_variant(self._h).decode()
+        self.offsets: Dict[str, np.ndarray] = {}
+        self.totals: Dict[str, int] = {}
+        for i, name in enumerate(ARRAYS):
+            offs = np.zeros(self.batch, np.int64)
+            self.totals[name] = int(lib.lq_plan_offsets(self._h, i, offs.ctypes.data_as(C.POINTER(C.c_int64))))
+            self.offsets[name] = offs
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().lq_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, device=None) -> torch.Tensor:
+        # torch's caching allocator returns 256-byte aligned blocks
+        return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device or "cuda")
+
+    def empty_outputs(self, device=None):
+        dev = device or "cuda"
+        return tuple(torch.empty(self.totals[k], dtype=torch.float64, device=dev) for k in ("x", "u", "lam"))
+
+
+def _data(d: Dict[str, torch.Tensor]) -> LqData:
+    return LqData(*[_ptr(d.get(k)) for k in INPUTS])
+
+
+def factor(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, info: torch.Tensor, stream=None):
+    lib = _lib.load()
+    dd = _data(data)
+    check(lib.lq_factor(plan.handle, C.byref(dd), _ptr(ws), _ptr(info), _stream(stream)), "lq_factor")
+
+
+def solve(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, lam, rel_res=None, iters=None,
+          info=None, tol: float = 1e-10, max_it: int = 0, check_res: bool = True, stream=None):
+    lib = _lib.load()
+    dd = _data(data)
+    o = LqSolveOpts(float(tol), int(max_it), int(bool(check_res)))
+    check(lib.lq_solve(plan.handle, C.byref(dd), _ptr(ws), C.byref(o), _ptr(x), _ptr(u), _ptr(lam),
+                       _ptr(rel_res), _ptr(iters), _ptr(info), _stream(stream)), "lq_solve")
+
+
+def solve_backward(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, lam, gx, gu,
+                   grads: Dict[str, torch.Tensor], rel_res=None, iters=None, info=None, tol: float = 1e-10,
+                   max_it: int = 0, check_res: bool = True, stream=None):
+    lib = _lib.load()
+    dd = _data(data)
+    o = LqSolveOpts(float(tol), int(max_it), int(bool(check_res)))
+    g = [grads.get(k) for k in ("A", "B", "Q", "R", "S", "q", "r", "f", "x0")]
+    check(lib.lq_solve_backward(plan.handle, C.byref(dd), _ptr(ws), C.byref(o), _ptr(x), _ptr(u), _ptr(lam),
+                                _ptr(gx), _ptr(gu), *[_ptr(t) for t in g], _ptr(rel_res), _ptr(iters),
+                                _ptr(info), _stream(stream)), "lq_solve_backward")
+
+
+# ---------------------------------------------------------------------------------------------
+# Packing of problems into the boundary layout (instance blocks back to back, row-major).
+
+def pack(problems, device="cuda", with_S=None, with_f=None) -> Dict[str, torch.Tensor]:
+    """Pack an LQProblem batch (uniform) or a list of instances into device float64 arrays."""
+    if hasattr(problems, "batched") and problems.batched:
+        p = problems
+        out = {}
+        for k in INPUTS:
+            a = getattr(p, k)
+            if a is None:
+                continue
+            out[k] = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to(device)
+        return out
+    insts = problems if isinstance(problems, (list, tuple)) else [problems]
+    out = {}
+    for k in INPUTS:
+        vals = [getattr(p, k) for p in insts]
+        if all(v is None for v in vals):
+            continue
+        flat = []
+        for p, v in zip(insts, vals):
+            if v is None:
+                shape = {"S": (p.N, p.nu, p.nx), "f": (p.N, p.nx)}[k]
+                v = np.zeros(shape)
+            flat.append(np.ascontiguousarray(v, dtype=np.float64).reshape(-1))
+        out[k] = torch.from_numpy(np.concatenate(flat)).to(device)
+    return out
+
+
+def unpack(plan: Plan, name: str, flat: torch.Tensor, i: int) -> np.ndarray:
+    """Instance i's block of output or input array `name` as (stages, dim) numpy array."""
+    N, nx, nu = int(plan.N[i]), int(plan.nx[i]), int(plan.nu[i])
+    shapes = {"x": (N, nx), "u": (N, nu), "lam": (N, nx), "A": (N, nx, nx), "B": (N, nx, nu),
+              "Q": (N + 1, nx, nx), "R": (N, nu, nu), "S": (N, nu, nx), "q": (N + 1, nx), "r": (N, nu),
+              "f": (N, nx), "x0": (nx,)}
+    shp = shapes[name]
+    n = int(np.prod(shp))
+    o = int(plan.offsets[name][i])
+    return flat[o:o + n].detach().cpu().numpy().reshape(shp)

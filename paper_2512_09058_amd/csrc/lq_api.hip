@@ -1,0 +1,293 @@
+// Host runtime of liblqkkt: plans, argument validation, workspace layout, kernel dispatch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lq_internal.hpp"
+
+namespace lq {
+size_t generic_factor_lds(int nx, int nu);
+size_t generic_solve_lds(int nx, int nu);
+hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F,
+                                 double* V, int32_t* info, size_t lds, hipStream_t st);
+hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, hipStream_t st);
+hipError_t launch_grad_generic(const GradArgs& a, hipStream_t st);
+
+// Size-specialised uniform-batch kernels (lq_small.hip); return false if no variant fits.
+bool small_variant_available(lq_mode mode, int nx, int nu);
+hipError_t launch_factor_small(lq_mode mode, int batch, int N, int nx, int nu, const lq_data& d,
+                               void* F, double* V, int32_t* info, hipStream_t st);
+hipError_t launch_solve_small(lq_mode mode, int N, int nx, int nu, const SolveArgs& a, hipStream_t st);
+}  // namespace lq
+
+using lq::Desc;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static const size_t kLdsLimit = 160 * 1024;
+
+enum Variant : int32_t { VAR_GENERIC = 0, VAR_SMALL = 1 };
+
+struct lq_plan {
+  int32_t batch = 0;
+  lq_mode mode = LQ_F64;
+  int32_t ckpt = 0;
+  bool uniform = true;
+  int32_t maxN = 0, maxnx = 0, maxnu = 0;
+  std::vector<int32_t> N, nx, nu;
+  std::vector<int64_t> off[LQ_ARR_COUNT];
+  int64_t total[LQ_ARR_COUNT] = {};
+  std::vector<Desc> desc_h;
+  Desc* desc_d = nullptr;
+  int device = 0;
+  size_t fbytes = 0;  // bytes per factor element
+  size_t offF = 0, offV = 0, offV2 = 0, offZB = 0, ws_bytes = 0;
+  size_t lds_factor = 0, lds_solve = 0;
+  Variant variant = VAR_GENERIC;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+extern "C" int lq_version(void) { return 100; }
+
+extern "C" const char* lq_last_error(void) { return g_err.c_str(); }
+
+extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx, const int32_t* nu,
+                              lq_mode mode, int32_t ckpt_stride, lq_plan** out) {
+  g_err.clear();
+  if (!out) return fail(LQ_EINVAL, "lq_plan_create: out is NULL");
+  *out = nullptr;
+  if (batch <= 0) return fail(LQ_EINVAL, "lq_plan_create: batch must be positive (got %d)", batch);
+  if (!N || !nx || !nu) return fail(LQ_EINVAL, "lq_plan_create: N, nx, nu host arrays are required");
+  if (mode != LQ_F64 && mode != LQ_MIXED_F32 && mode != LQ_MIXED_BF16)
+    return fail(LQ_EINVAL, "lq_plan_create: unknown mode %d", (int)mode);
+  if (ckpt_stride < 0) return fail(LQ_EINVAL, "lq_plan_create: ckpt_stride must be >= 0");
+  if (ckpt_stride > 0) return fail(LQ_EUNSUPPORTED, "lq_plan_create: factor checkpointing is not built yet");
+  lq_plan* p = new (std::nothrow) lq_plan;
+  if (!p) return fail(LQ_ENOMEM, "lq_plan_create: host allocation failed");
+  p->batch = batch;
+  p->mode = mode;
+  p->ckpt = ckpt_stride;
+  p->N.assign(N, N + batch);
+  p->nx.assign(nx, nx + batch);
+  p->nu.assign(nu, nu + batch);
+  for (int i = 0; i < batch; ++i) {
+    if (N[i] <= 0 || nx[i] <= 0 || nu[i] <= 0) {
+      delete p;
+      return fail(LQ_EINVAL, "lq_plan_create: instance %d has non-positive size (N=%d nx=%d nu=%d)", i,
+                  N[i], nx[i], nu[i]);
+    }
+    if (N[i] > (1 << 24) || nx[i] > 4096 || nu[i] > 4096) {
+      delete p;
+      return fail(LQ_EUNSUPPORTED, "lq_plan_create: instance %d too large", i);
+    }
+    p->maxN = std::max(p->maxN, N[i]);
+    p->maxnx = std::max(p->maxnx, nx[i]);
+    p->maxnu = std::max(p->maxnu, nu[i]);
+    if (N[i] != N[0] || nx[i] != nx[0] || nu[i] != nu[0]) p->uniform = false;
+  }
+  p->fbytes = mode == LQ_F64 ? sizeof(double) : sizeof(float);
+  // packed layouts and per-instance descriptors
+  for (int a = 0; a < LQ_ARR_COUNT; ++a) p->off[a].resize(batch);
+  p->desc_h.resize(batch);
+  int64_t acc[LQ_ARR_COUNT] = {};
+  int64_t aF = 0, aV = 0, aV2 = 0, aZB = 0;
+  size_t ldsf = 0, ldss = 0;
+  for (int i = 0; i < batch; ++i) {
+    const int64_t n = N[i], x = nx[i], u = nu[i];
+    const int64_t sz[LQ_ARR_COUNT] = {n * x * x, n * x * u, (n + 1) * x * x, n * u * u, n * u * x,
+                                      (n + 1) * x, n * u, n * x, x, n * x, n * u, n * x};
+    for (int a = 0; a < LQ_ARR_COUNT; ++a) {
+      p->off[a][i] = acc[a];
+      acc[a] += sz[a];
+    }
+    Desc& D = p->desc_h[i];
+    D.N = N[i]; D.nx = nx[i]; D.nu = nu[i]; D.pad = 0;
+    D.oA = p->off[LQ_ARR_A][i]; D.oB = p->off[LQ_ARR_B][i]; D.oQ = p->off[LQ_ARR_Q][i];
+    D.oR = p->off[LQ_ARR_R][i]; D.oS = p->off[LQ_ARR_S][i]; D.oq = p->off[LQ_ARR_q][i];
+    D.or_ = p->off[LQ_ARR_r][i]; D.of = p->off[LQ_ARR_f][i]; D.ox0 = p->off[LQ_ARR_x0][i];
+    D.ox = p->off[LQ_ARR_x][i]; D.ou = p->off[LQ_ARR_u][i]; D.olam = p->off[LQ_ARR_lam][i];
+    D.oF = aF; aF += (n + 1) * lq::stage_factor_elems(nx[i], nu[i]);
+    D.oV = aV; aV += n * u + (n + 1) * x;
+    D.oV2 = aV2; aV2 += n * u + (n + 1) * x + n * x;
+    D.oZB = aZB; aZB += n * (2 * x + u);
+    ldsf = std::max(ldsf, lq::generic_factor_lds(nx[i], nu[i]));
+    ldss = std::max(ldss, lq::generic_solve_lds(nx[i], nu[i]));
+  }
+  for (int a = 0; a < LQ_ARR_COUNT; ++a) p->total[a] = acc[a];
+  p->lds_factor = ldsf;
+  p->lds_solve = ldss;
+  p->variant = (p->uniform && lq::small_variant_available(mode, nx[0], nu[0])) ? VAR_SMALL : VAR_GENERIC;
+  if (p->variant == VAR_GENERIC && ldsf > kLdsLimit) {
+    delete p;
+    return fail(LQ_EUNSUPPORTED, "lq_plan_create: stage tile needs %zu bytes of LDS (limit %zu)", ldsf,
+                kLdsLimit);
+  }
+  p->offF = 0;
+  p->offV = align256(p->offF + (size_t)aF * p->fbytes);
+  p->offV2 = align256(p->offV + (size_t)aV * sizeof(double));
+  p->offZB = align256(p->offV2 + (size_t)aV2 * sizeof(double));
+  p->ws_bytes = align256(p->offZB + (size_t)aZB * sizeof(double));
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(LQ_EHIP, "lq_plan_create: hipGetDevice failed");
+  }
+  if (hipMalloc((void**)&p->desc_d, sizeof(Desc) * batch) != hipSuccess) {
+    delete p;
+    return fail(LQ_ENOMEM, "lq_plan_create: descriptor table allocation failed");
+  }
+  if (hipMemcpy(p->desc_d, p->desc_h.data(), sizeof(Desc) * batch, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(p->desc_d);
+    delete p;
+    return fail(LQ_EHIP, "lq_plan_create: descriptor upload failed");
+  }
+  *out = p;
+  return LQ_OK;
+}
+
+extern "C" void lq_plan_destroy(lq_plan* p) {
+  if (!p) return;
+  if (p->desc_d) hipFree(p->desc_d);
+  delete p;
+}
+
+extern "C" size_t lq_plan_workspace_bytes(const lq_plan* p) { return p ? p->ws_bytes : 0; }
+
+extern "C" int64_t lq_plan_offsets(const lq_plan* p, lq_array which, int64_t* offs) {
+  if (!p || which < 0 || which >= LQ_ARR_COUNT) {
+    fail(LQ_EINVAL, "lq_plan_offsets: invalid plan or array");
+    return -1;
+  }
+  if (offs) memcpy(offs, p->off[which].data(), sizeof(int64_t) * p->batch);
+  return p->total[which];
+}
+
+extern "C" const char* lq_plan_variant(const lq_plan* p) {
+  if (!p) return "";
+  return p->variant == VAR_SMALL ? "small" : "generic";
+}
+
+static int check_common(const lq_plan* p, const lq_data* d, void* ws, const char* fn) {
+  if (!p) return fail(LQ_EINVAL, "%s: plan is NULL", fn);
+  if (!d) return fail(LQ_EINVAL, "%s: data is NULL", fn);
+  if (!d->A || !d->B || !d->Q || !d->R || !d->q || !d->r || !d->x0)
+    return fail(LQ_EINVAL, "%s: A, B, Q, R, q, r, x0 are required", fn);
+  if (!ws) return fail(LQ_EINVAL, "%s: workspace is NULL", fn);
+  if (((uintptr_t)ws) & 255) return fail(LQ_EINVAL, "%s: workspace must be 256-byte aligned", fn);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(LQ_EINVAL, "%s: current device %d differs from the plan's device %d", fn, dev, p->device);
+  return LQ_OK;
+}
+
+static int launch_status(hipError_t e, const char* fn) {
+  if (e != hipSuccess) return fail(LQ_EHIP, "%s: launch failed: %s", fn, hipGetErrorString(e));
+  return LQ_OK;
+}
+
+extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* info, hipStream_t st) {
+  g_err.clear();
+  int rc = check_common(p, d, ws, "lq_factor");
+  if (rc) return rc;
+  if (!info) return fail(LQ_EINVAL, "lq_factor: info is NULL");
+  char* w = (char*)ws;
+  void* F = w + p->offF;
+  double* V = (double*)(w + p->offV);
+  hipError_t e;
+  if (p->variant == VAR_SMALL)
+    e = lq::launch_factor_small(p->mode, p->batch, p->N[0], p->nx[0], p->nu[0], *d, F, V, info, st);
+  else
+    e = lq::launch_factor_generic(p->mode, p->desc_d, p->batch, *d, F, V, info, p->lds_factor, st);
+  return launch_status(e, "lq_factor");
+}
+
+static lq::SolveArgs base_args(const lq_plan* p, const lq_data* d, void* ws, const lq_solve_opts* o) {
+  char* w = (char*)ws;
+  lq::SolveArgs a;
+  memset(&a, 0, sizeof a);
+  a.desc = p->desc_d;
+  a.batch = p->batch;
+  a.d = *d;
+  a.F = w + p->offF;
+  a.V = (const double*)(w + p->offV);
+  a.V2 = (double*)(w + p->offV2);
+  a.tol = o->tol;
+  a.max_it = o->max_it;
+  a.check = o->check;
+  return a;
+}
+
+static int check_opts(const lq_solve_opts* o, const char* fn) {
+  if (!o) return fail(LQ_EINVAL, "%s: opts is NULL", fn);
+  if (!(o->tol >= 0.0)) return fail(LQ_EINVAL, "%s: tol must be >= 0", fn);
+  if (o->max_it < 0 || o->max_it > 1000) return fail(LQ_EINVAL, "%s: max_it must be in [0, 1000]", fn);
+  return LQ_OK;
+}
+
+extern "C" int lq_solve(const lq_plan* p, const lq_data* d, void* ws, const lq_solve_opts* o, double* x,
+                        double* u, double* lam, double* rel_res, int32_t* iters, int32_t* info,
+                        hipStream_t st) {
+  g_err.clear();
+  int rc = check_common(p, d, ws, "lq_solve");
+  if (rc) return rc;
+  if ((rc = check_opts(o, "lq_solve"))) return rc;
+  if (!x || !u || !lam) return fail(LQ_EINVAL, "lq_solve: x, u, lam are required");
+  if (!info) return fail(LQ_EINVAL, "lq_solve: info is NULL");
+  lq::SolveArgs a = base_args(p, d, ws, o);
+  a.x = x; a.u = u; a.lam = lam;
+  a.rhs = lq::RHS_PRIMAL;
+  a.rel_res = rel_res; a.iters = iters; a.info = info;
+  hipError_t e;
+  if (p->variant == VAR_SMALL)
+    e = lq::launch_solve_small(p->mode, p->N[0], p->nx[0], p->nu[0], a, st);
+  else
+    e = lq::launch_solve_generic(p->mode, a, p->lds_solve, st);
+  return launch_status(e, "lq_solve");
+}
+
+extern "C" int lq_solve_backward(const lq_plan* p, const lq_data* d, void* ws, const lq_solve_opts* o,
+                                 const double* x, const double* u, const double* lam, const double* gx,
+                                 const double* gu, double* gA, double* gB, double* gQ, double* gR,
+                                 double* gS, double* gq, double* gr, double* gf, double* gx0,
+                                 double* rel_res, int32_t* iters, int32_t* info, hipStream_t st) {
+  g_err.clear();
+  int rc = check_common(p, d, ws, "lq_solve_backward");
+  if (rc) return rc;
+  if ((rc = check_opts(o, "lq_solve_backward"))) return rc;
+  if (!x || !u || !lam || !gx || !gu) return fail(LQ_EINVAL, "lq_solve_backward: x, u, lam, gx, gu are required");
+  if (!gA || !gB || !gQ || !gR || !gq || !gr || !gx0)
+    return fail(LQ_EINVAL, "lq_solve_backward: gA, gB, gQ, gR, gq, gr, gx0 are required");
+  if (!info) return fail(LQ_EINVAL, "lq_solve_backward: info is NULL");
+  char* w = (char*)ws;
+  double* ZB = (double*)(w + p->offZB);
+  lq::SolveArgs a = base_args(p, d, ws, o);
+  a.x = ZB;
+  a.out_is_zb = 1;
+  a.gx = gx; a.gu = gu;
+  a.rhs = lq::RHS_ADJOINT;
+  a.rel_res = rel_res; a.iters = iters; a.info = info;
+  hipError_t e = lq::launch_solve_generic(p->mode, a, p->lds_solve, st);
+  if ((rc = launch_status(e, "lq_solve_backward"))) return rc;
+  lq::GradArgs g;
+  g.desc = p->desc_d; g.batch = p->batch; g.d = *d;
+  g.x = x; g.u = u; g.lam = lam; g.ZB = ZB;
+  g.gA = gA; g.gB = gB; g.gQ = gQ; g.gR = gR; g.gS = gS; g.gq = gq; g.gr = gr; g.gf = gf; g.gx0 = gx0;
+  e = lq::launch_grad_generic(g, st);
+  return launch_status(e, "lq_solve_backward");
+}

@@ -1,0 +1,670 @@
+// Generic kernels: one workgroup per instance, stage matrices staged in LDS, runtime sizes.
+//
+// They cover every (N, nx, nu) whose stage tile fits in LDS and every batch shape (uniform
+// or ragged, via the per-instance descriptors).  The size-specialised kernels are faster;
+// these are the general path and the one the uneven-batch scheduler falls back to.
+//
+// Factor sweep (paper, Alg. "factor-block-column-riccati" with one interval): per stage,
+// backward in time,
+//   V_k   = [B_k^T; A_k^T] L^Q_{k+1}                      (trmm)
+//   Hhat  = [[R_k, S_k],[S_k^T, Q_k]] + V_k V_k^T          (syrk)
+//   chol(Hhat) = [[L^R_k, 0],[L^S_k, L^Q_k]]               (potrf, always float64)
+// starting from L^Q_N = chol(Q_N).  At k = 0 only the first nu pivot columns are needed
+// (x_0 is fixed), which gives L^R_0 and L^S_0.
+//
+// Right-hand-side sweeps (the substitution phase of the block factorisation):
+//   backward: p_N = q_N;  w = L^Q_{k+1} L^Q_{k+1}^T f_k + p_{k+1};
+//             rbar_k = (L^R_k)^{-1} (r_k + B_k^T w);  p_k = q_k + A_k^T w - L^S_k rbar_k
+//   forward:  x_0 = x_init;  u_k = -(L^R_k)^{-T} ((L^S_k)^T x_k + rbar_k);
+//             x_{k+1} = A_k x_k + B_k u_k + f_k;  lam_k = L^Q_{k+1} L^Q_{k+1}^T x_{k+1} + p_{k+1}
+// KKT residual (eq. opt-cond-ocp-eq, x_0 = x_init):
+//   rho_u,k = -r_k - (R_k u_k + S_k x_k + B_k^T lam_k)
+//   rho_x,k = -q_k - (S_k^T u_k + Q_k x_k + A_k^T lam_k - lam_{k-1})     (1 <= k < N)
+//   rho_x,N = -q_N - (Q_N x_N - lam_{N-1})
+//   rho_l,k = -f_k - (A_k x_k + B_k u_k - x_{k+1})
+// A correction solves K dz = rho, i.e. the sweeps above with (r, q, f, x_init) replaced by
+// (-rho_u, -rho_x, -rho_l, 0).  The adjoint system K zbar = (gu, gx, 0) uses (-gu, -gx, 0, 0).
+#include <math.h>
+
+#include "lq_internal.hpp"
+
+namespace lq {
+
+__device__ __forceinline__ double rsqrt_f64(double a) {
+  // hardware estimate (~2^-24) and two Newton steps: y <- y (3/2 - a/2 y^2)
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+template <typename T>
+__device__ __forceinline__ double rnd(double v) {
+  return (double)(T)v;
+}
+
+// Right-looking Cholesky of the leading n x n block of H (row-major, leading dim ld), for
+// pivot columns 0..ncol-1 (trailing update restricted to those columns).  Writes 1/L_jj to
+// dinv.  Non-positive pivots are replaced by 1 and reported through *bad (1: not positive
+// definite, 2: non-finite), the first time only.
+__device__ void potrf_lds(double* H, int ld, int n, int ncol, double* dinv, int* bad) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < ncol; ++j) {
+    __syncthreads();
+    double dj = H[j * ld + j];
+    const bool fin = isfinite(dj);
+    if (!(fin && dj > 0.0)) {
+      if (tid == 0 && *bad == 0) *bad = fin ? 1 : 2;
+      dj = 1.0;
+    }
+    const double inv = rsqrt_f64(dj);
+    for (int i = j + 1 + tid; i < n; i += nt) H[i * ld + j] *= inv;
+    if (tid == 0) {
+      H[j * ld + j] = dj * inv;
+      dinv[j] = inv;
+    }
+    __syncthreads();
+    const int nr = n - j - 1, nc = ncol - j - 1;
+    for (int e = tid; e < nr * nc; e += nt) {
+      const int i = j + 1 + e / nc, c = j + 1 + e % nc;
+      if (c <= i) H[i * ld + c] -= H[i * ld + j] * H[c * ld + j];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename TF, typename TP>
+__global__ void __launch_bounds__(128) k_factor_generic(const Desc* __restrict__ desc, int batch,
+                                                        lq_data d, TF* __restrict__ F,
+                                                        double* __restrict__ Vws,
+                                                        int32_t* __restrict__ info) {
+  extern __shared__ double smem[];
+  __shared__ int s_bad, s_info;
+  const int b = blockIdx.x;
+  if (b >= batch) return;
+  const Desc D = desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu, nux = nx + nu;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* H = smem;              // nux*nux   (stage tile; also stages C = [B A])
+  double* Lq = H + nux * nux;    // nx*nx     L^Q_{k+1}, full square, zero above the diagonal
+  double* Vm = Lq + nx * nx;     // nux*nx
+  double* pn = Vm + nux * nx;    // nx        p_{k+1}
+  double* w = pn + nx;           // nx
+  double* tq = w + nx;           // nux       (rhat, qhat)
+  double* dinv = tq + nux;       // nux
+  double* t1 = dinv + nux;       // nx
+
+  const int64_t fs = stage_factor_elems(nx, nu);
+  TF* Fi = F + D.oF;
+  double* rbar = Vws + D.oV;              // N*nu
+  double* pv = Vws + D.oV + (int64_t)N * nu;  // (N+1)*nx
+  const double* A = d.A + D.oA;
+  const double* Bm = d.B + D.oB;
+  const double* Q = d.Q + D.oQ;
+  const double* R = d.R + D.oR;
+  const double* S = d.S ? d.S + D.oS : nullptr;
+  const double* q = d.q + D.oq;
+  const double* r = d.r + D.or_;
+  const double* f = d.f ? d.f + D.of : nullptr;
+
+  if (tid == 0) { s_bad = 0; s_info = 0; }
+  // ---- stage N: L^Q_N = chol(sym Q_N), p_N = q_N
+  {
+    const double* QN = Q + (int64_t)N * nx * nx;
+    for (int e = tid; e < nx * nx; e += nt) {
+      const int i = e / nx, j = e % nx;
+      H[e] = 0.5 * (QN[i * nx + j] + QN[j * nx + i]);
+    }
+    for (int i = tid; i < nx; i += nt) pn[i] = q[(int64_t)N * nx + i];
+    __syncthreads();
+    potrf_lds(H, nx, nx, nx, dinv, &s_bad);
+    if (tid == 0 && s_bad) { s_info = s_bad == 2 ? LQ_INFO_NONFINITE : N + 1; s_bad = 0; }
+    TF* FN = Fi + (int64_t)N * fs;
+    for (int e = tid; e < nx * nx; e += nt) {
+      const int i = e / nx, j = e % nx;
+      const double v = j <= i ? rnd<TF>(H[e]) : 0.0;
+      Lq[e] = v;
+      if (j <= i) FN[off_LQ(nx, nu) + i * (i + 1) / 2 + j] = (TF)v;
+    }
+    for (int i = tid; i < nx; i += nt) FN[off_dQ(nx, nu) + i] = (TF)dinv[i];
+    for (int i = tid; i < nx; i += nt) pv[(int64_t)N * nx + i] = pn[i];
+    __syncthreads();
+  }
+
+  for (int k = N - 1; k >= 0; --k) {
+    const double* Ak = A + (int64_t)k * nx * nx;
+    const double* Bk = Bm + (int64_t)k * nx * nu;
+    // C = [B_k A_k] (nx x nux) staged in H with leading dimension nux
+    for (int e = tid; e < nx * nux; e += nt) {
+      const int m = e / nux, i = e % nux;
+      H[e] = i < nu ? Bk[m * nu + i] : Ak[m * nx + (i - nu)];
+    }
+    // t1 = Lq^T f_k ; then w = Lq t1 + p_{k+1}
+    for (int j = tid; j < nx; j += nt) {
+      double s = 0.0;
+      if (f) {
+        const double* fk = f + (int64_t)k * nx;
+        for (int m = j; m < nx; ++m) s += Lq[m * nx + j] * fk[m];
+      }
+      t1[j] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < nx; i += nt) {
+      double s = pn[i];
+      if (f)
+        for (int j = 0; j <= i; ++j) s += Lq[i * nx + j] * t1[j];
+      w[i] = s;
+    }
+    __syncthreads();
+    // (rhat, qhat) = (r_k, q_k) + C^T w ;  V = C^T Lq in the product precision
+    for (int i = tid; i < nux; i += nt) {
+      double s = i < nu ? r[(int64_t)k * nu + i] : (k > 0 ? q[(int64_t)k * nx + (i - nu)] : 0.0);
+      for (int m = 0; m < nx; ++m) s += H[m * nux + i] * w[m];
+      tq[i] = s;
+    }
+    for (int e = tid; e < nux * nx; e += nt) {
+      const int i = e / nx, j = e % nx;
+      TP s = 0;
+      for (int m = j; m < nx; ++m) s += (TP)H[m * nux + i] * (TP)Lq[m * nx + j];
+      Vm[e] = (double)s;
+    }
+    __syncthreads();
+    // Hhat = [[R,S],[S^T,Q]] + V V^T (lower triangle; at k = 0 only the first nu columns)
+    const int ncol = k > 0 ? nux : nu;
+    const double* Rk = R + (int64_t)k * nu * nu;
+    const double* Qk = Q + (int64_t)k * nx * nx;
+    const double* Sk = S ? S + (int64_t)k * nu * nx : nullptr;
+    for (int e = tid; e < nux * nux; e += nt) {
+      const int i = e / nux, j = e % nux;
+      if (j > i || j >= ncol) continue;
+      double h;
+      if (i < nu) h = 0.5 * (Rk[i * nu + j] + Rk[j * nu + i]);
+      else if (j < nu) h = Sk ? Sk[j * nx + (i - nu)] : 0.0;
+      else h = 0.5 * (Qk[(i - nu) * nx + (j - nu)] + Qk[(j - nu) * nx + (i - nu)]);
+      TP s = 0;
+      for (int m = 0; m < nx; ++m) s += (TP)Vm[i * nx + m] * (TP)Vm[j * nx + m];
+      H[e] = h + (double)s;
+    }
+    __syncthreads();
+    potrf_lds(H, nux, nux, ncol, dinv, &s_bad);
+    if (tid == 0 && s_bad) {
+      if (s_info == 0) s_info = s_bad == 2 ? LQ_INFO_NONFINITE : k + 1;
+      s_bad = 0;
+    }
+    // round to the storage precision, store, keep L^Q_k for the next stage
+    TF* Fk = Fi + (int64_t)k * fs;
+    for (int e = tid; e < nux * nux; e += nt) {
+      const int i = e / nux, j = e % nux;
+      if (j > i || j >= ncol) continue;
+      const double v = rnd<TF>(H[e]);
+      H[e] = v;
+      if (i < nu) Fk[i * (i + 1) / 2 + j] = (TF)v;
+      else if (j < nu) Fk[off_LS(nx, nu) + (i - nu) * nu + j] = (TF)v;
+      else Fk[off_LQ(nx, nu) + (i - nu) * (i - nu + 1) / 2 + (j - nu)] = (TF)v;
+    }
+    for (int i = tid; i < ncol; i += nt) {
+      const double v = rnd<TF>(dinv[i]);
+      dinv[i] = v;
+      if (i < nu) Fk[off_dR(nx, nu) + i] = (TF)v;
+      else Fk[off_dQ(nx, nu) + (i - nu)] = (TF)v;
+    }
+    __syncthreads();
+    // rbar = L^R^{-1} rhat (forward substitution), p_k = qhat - L^S rbar
+    if (tid == 0) {
+      for (int i = 0; i < nu; ++i) {
+        double s = tq[i];
+        for (int j = 0; j < i; ++j) s -= H[i * nux + j] * tq[j];
+        tq[i] = s * dinv[i];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nu; i += nt) rbar[(int64_t)k * nu + i] = tq[i];
+    if (k > 0) {
+      for (int i = tid; i < nx; i += nt) {
+        double s = tq[nu + i];
+        for (int j = 0; j < nu; ++j) s -= H[(nu + i) * nux + j] * tq[j];
+        pn[i] = s;
+        pv[(int64_t)k * nx + i] = s;
+      }
+      for (int e = tid; e < nx * nx; e += nt) {
+        const int i = e / nx, j = e % nx;
+        Lq[e] = j <= i ? H[(nu + i) * nux + (nu + j)] : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[b] = s_info;
+}
+
+// ------------------------------------------------------------------------------------------
+// Solve: forward rollout, then (residual + correction backward sweep, forward correction)
+// repeated until rel_res <= tol or max_it corrections.
+
+struct InstView {
+  int N, nx, nu;
+  const double *A, *B, *Q, *R, *S, *q, *r, *f, *x0;  // problem data (S, f nullable)
+  const double *gx, *gu;                              // adjoint right-hand side
+  int rhs;
+  double *x, *u, *lam;                                // iterate
+};
+
+// Right-hand-side accessors: (r_k, q_k, f_k, x_init) of the system being solved.
+__device__ __forceinline__ double rhs_r(const InstView& v, int k, int i) {
+  return v.rhs == RHS_PRIMAL ? v.r[(int64_t)k * v.nu + i] : -v.gu[(int64_t)k * v.nu + i];
+}
+__device__ __forceinline__ double rhs_q(const InstView& v, int k, int i) {  // 1 <= k <= N
+  return v.rhs == RHS_PRIMAL ? v.q[(int64_t)k * v.nx + i] : -v.gx[(int64_t)(k - 1) * v.nx + i];
+}
+__device__ __forceinline__ double rhs_f(const InstView& v, int k, int i) {
+  return (v.rhs == RHS_PRIMAL && v.f) ? v.f[(int64_t)k * v.nx + i] : 0.0;
+}
+__device__ __forceinline__ double rhs_x0(const InstView& v, int i) {
+  return v.rhs == RHS_PRIMAL ? v.x0[i] : 0.0;
+}
+
+template <typename TF>
+struct FactView {
+  const TF* F;
+  int64_t fs;
+  int nx, nu;
+  __device__ double LR(int k, int i, int j) const { return (double)F[k * fs + i * (i + 1) / 2 + j]; }
+  __device__ double dR(int k, int i) const { return (double)F[k * fs + off_dR(nx, nu) + i]; }
+  __device__ double LS(int k, int i, int j) const { return (double)F[k * fs + off_LS(nx, nu) + i * nu + j]; }
+  __device__ double LQ(int k, int i, int j) const {
+    return (double)F[k * fs + off_LQ(nx, nu) + i * (i + 1) / 2 + j];
+  }
+};
+
+// forward sweep; mode 0: z = result (x_0 = x_init, f = f_k);  mode 1: z += result (x_0 = 0,
+// f = flam_k from the preceding residual pass)
+template <typename TF>
+__device__ void fwd_sweep(const InstView& v, const FactView<TF>& fv, const double* rbar,
+                          const double* pv, const double* flam, int mode, double* sm) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int N = v.N, nx = v.nx, nu = v.nu;
+  double* xc = sm;        // nx
+  double* xn = xc + nx;   // nx
+  double* t = xn + nx;    // nu
+  double* uu = t + nu;    // nu
+  double* t2 = uu + nu;   // nx
+  for (int i = tid; i < nx; i += nt) xc[i] = mode == 0 ? rhs_x0(v, i) : 0.0;
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    for (int j = tid; j < nu; j += nt) {
+      double s = rbar[(int64_t)k * nu + j];
+      for (int i = 0; i < nx; ++i) s += fv.LS(k, i, j) * xc[i];
+      t[j] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int j = nu - 1; j >= 0; --j) {
+        double s = t[j];
+        for (int i = j + 1; i < nu; ++i) s -= fv.LR(k, i, j) * uu[i];
+        uu[j] = s * fv.dR(k, j);
+      }
+      for (int j = 0; j < nu; ++j) uu[j] = -uu[j];
+    }
+    __syncthreads();
+    const double* Ak = v.A + (int64_t)k * nx * nx;
+    const double* Bk = v.B + (int64_t)k * nx * nu;
+    for (int i = tid; i < nx; i += nt) {
+      double s = mode == 0 ? rhs_f(v, k, i) : flam[(int64_t)k * nx + i];
+      for (int m = 0; m < nx; ++m) s += Ak[i * nx + m] * xc[m];
+      for (int m = 0; m < nu; ++m) s += Bk[i * nu + m] * uu[m];
+      xn[i] = s;
+    }
+    __syncthreads();
+    for (int j = tid; j < nx; j += nt) {
+      double s = 0.0;
+      for (int i = j; i < nx; ++i) s += fv.LQ(k + 1, i, j) * xn[i];
+      t2[j] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < nx; i += nt) {
+      double s = pv[(int64_t)(k + 1) * nx + i];
+      for (int j = 0; j <= i; ++j) s += fv.LQ(k + 1, i, j) * t2[j];
+      double* lk = v.lam + (int64_t)k * nx;
+      double* xk = v.x + (int64_t)k * nx;
+      if (mode == 0) { lk[i] = s; xk[i] = xn[i]; }
+      else { lk[i] += s; xk[i] += xn[i]; }
+    }
+    for (int j = tid; j < nu; j += nt) {
+      double* uk = v.u + (int64_t)k * nu;
+      if (mode == 0) uk[j] = uu[j];
+      else uk[j] += uu[j];
+    }
+    for (int i = tid; i < nx; i += nt) xc[i] = xn[i];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Residual of the current iterate (returns rel_res); if `sweep`, also the backward sweep of
+// the correction right-hand side into (rbar2, p2) and -rho_l into flam.
+template <typename TF>
+__device__ double resid_bwd(const InstView& v, const FactView<TF>& fv, bool sweep, double* rbar2,
+                            double* p2, double* flam, double* sm, double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int N = v.N, nx = v.nx, nu = v.nu, nux = nx + nu;
+  double* pn = sm;          // nx   p2_{k+1}
+  double* rx = pn + nx;     // nx   rho_x,k
+  double* ru = rx + nx;     // nu   rho_u,k
+  double* rl = ru + nu;     // nx   rho_l,k
+  double* w = rl + nx;      // nx
+  double* t1 = w + nx;      // nx
+  double* tq = t1 + nx;     // nux
+  double mr = 0.0, mb = 0.0;
+  // stage N
+  for (int i = tid; i < nx; i += nt) {
+    const double* QN = v.Q + (int64_t)N * nx * nx;
+    const double* xN = v.x + (int64_t)(N - 1) * nx;
+    double s = 0.0;
+    for (int j = 0; j < nx; ++j) s += 0.5 * (QN[i * nx + j] + QN[j * nx + i]) * xN[j];
+    const double qi = rhs_q(v, N, i);
+    const double rho = -qi - (s - v.lam[(int64_t)(N - 1) * nx + i]);
+    mr = fmax(mr, fabs(rho));
+    mb = fmax(mb, fabs(qi));
+    pn[i] = -rho;
+    if (sweep) p2[(int64_t)N * nx + i] = -rho;
+  }
+  __syncthreads();
+  for (int k = N - 1; k >= 0; --k) {
+    const double* Ak = v.A + (int64_t)k * nx * nx;
+    const double* Bk = v.B + (int64_t)k * nx * nu;
+    const double* Rk = v.R + (int64_t)k * nu * nu;
+    const double* Qk = v.Q + (int64_t)k * nx * nx;
+    const double* Sk = v.S ? v.S + (int64_t)k * nu * nx : nullptr;
+    const double* xk = k > 0 ? v.x + (int64_t)(k - 1) * nx : nullptr;  // x_k (k >= 1)
+    const double* xk1 = v.x + (int64_t)k * nx;                         // x_{k+1}
+    const double* uk = v.u + (int64_t)k * nu;
+    const double* lk = v.lam + (int64_t)k * nx;
+    const double* lkm = k > 0 ? v.lam + (int64_t)(k - 1) * nx : nullptr;
+#define XK(m) (k > 0 ? xk[m] : rhs_x0(v, m))
+    for (int i = tid; i < nu; i += nt) {
+      double s = 0.0, sb = 0.0;
+      for (int j = 0; j < nu; ++j) s += 0.5 * (Rk[i * nu + j] + Rk[j * nu + i]) * uk[j];
+      if (Sk)
+        for (int m = 0; m < nx; ++m) {
+          s += Sk[i * nx + m] * XK(m);
+          if (k == 0) sb += Sk[i * nx + m] * XK(m);
+        }
+      for (int m = 0; m < nx; ++m) s += Bk[m * nu + i] * lk[m];
+      const double ri = rhs_r(v, k, i);
+      const double rho = -ri - s;
+      ru[i] = rho;
+      mr = fmax(mr, fabs(rho));
+      mb = fmax(mb, fabs(ri + sb));
+    }
+    for (int i = tid; i < nx; i += nt) {
+      double s = -xk1[i], sb = 0.0;
+      for (int m = 0; m < nx; ++m) {
+        s += Ak[i * nx + m] * XK(m);
+        if (k == 0) sb += Ak[i * nx + m] * XK(m);
+      }
+      for (int m = 0; m < nu; ++m) s += Bk[i * nu + m] * uk[m];
+      const double fi = rhs_f(v, k, i);
+      const double rho = -fi - s;
+      rl[i] = rho;
+      mr = fmax(mr, fabs(rho));
+      mb = fmax(mb, fabs(fi + sb));
+      if (k > 0) {
+        double s2 = -lkm[i];
+        if (Sk)
+          for (int j = 0; j < nu; ++j) s2 += Sk[j * nx + i] * uk[j];
+        for (int m = 0; m < nx; ++m) s2 += 0.5 * (Qk[i * nx + m] + Qk[m * nx + i]) * xk[m];
+        for (int m = 0; m < nx; ++m) s2 += Ak[m * nx + i] * lk[m];
+        const double qi = rhs_q(v, k, i);
+        const double rho2 = -qi - s2;
+        rx[i] = rho2;
+        mr = fmax(mr, fabs(rho2));
+        mb = fmax(mb, fabs(qi));
+      }
+    }
+#undef XK
+    __syncthreads();
+    if (sweep) {
+      // correction right-hand side: r = -rho_u, q = -rho_x, f = -rho_l, x_init = 0
+      for (int i = tid; i < nx; i += nt) flam[(int64_t)k * nx + i] = -rl[i];
+      for (int j = tid; j < nx; j += nt) {
+        double s = 0.0;
+        for (int m = j; m < nx; ++m) s += fv.LQ(k + 1, m, j) * (-rl[m]);
+        t1[j] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < nx; i += nt) {
+        double s = pn[i];
+        for (int j = 0; j <= i; ++j) s += fv.LQ(k + 1, i, j) * t1[j];
+        w[i] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < nux; i += nt) {
+        double s;
+        if (i < nu) {
+          s = -ru[i];
+          for (int m = 0; m < nx; ++m) s += Bk[m * nu + i] * w[m];
+        } else {
+          s = k > 0 ? -rx[i - nu] : 0.0;
+          for (int m = 0; m < nx; ++m) s += Ak[m * nx + (i - nu)] * w[m];
+        }
+        tq[i] = s;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int i = 0; i < nu; ++i) {
+          double s = tq[i];
+          for (int j = 0; j < i; ++j) s -= fv.LR(k, i, j) * tq[j];
+          tq[i] = s * fv.dR(k, i);
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < nu; i += nt) rbar2[(int64_t)k * nu + i] = tq[i];
+      if (k > 0)
+        for (int i = tid; i < nx; i += nt) {
+          double s = tq[nu + i];
+          for (int j = 0; j < nu; ++j) s -= fv.LS(k, i, j) * tq[j];
+          pn[i] = s;
+          p2[(int64_t)k * nx + i] = s;
+        }
+    }
+    __syncthreads();
+  }
+  mr = block_max(mr, red);
+  mb = block_max(mb, red);
+  return mb > 0.0 ? mr / mb : mr;
+}
+
+template <typename TF>
+__global__ void __launch_bounds__(128) k_solve_generic(SolveArgs a, int64_t fs_unused) {
+  extern __shared__ double sm[];
+  __shared__ double red[128];
+  const int b = blockIdx.x;
+  if (b >= a.batch) return;
+  const Desc D = a.desc[b];
+  InstView v;
+  v.N = D.N; v.nx = D.nx; v.nu = D.nu;
+  v.A = a.d.A + D.oA; v.B = a.d.B + D.oB; v.Q = a.d.Q + D.oQ; v.R = a.d.R + D.oR;
+  v.S = a.d.S ? a.d.S + D.oS : nullptr; v.q = a.d.q + D.oq; v.r = a.d.r + D.or_;
+  v.f = a.d.f ? a.d.f + D.of : nullptr; v.x0 = a.d.x0 + D.ox0;
+  v.rhs = a.rhs;
+  v.gx = a.gx ? a.gx + D.ox : nullptr;
+  v.gu = a.gu ? a.gu + D.ou : nullptr;
+  if (a.out_is_zb) {
+    v.x = a.x + D.oZB;
+    v.u = a.x + D.oZB + (int64_t)D.N * D.nx;
+    v.lam = a.x + D.oZB + (int64_t)D.N * (D.nx + D.nu);
+  } else {
+    v.x = a.x + D.ox; v.u = a.u + D.ou; v.lam = a.lam + D.olam;
+  }
+  FactView<TF> fv;
+  fv.F = (const TF*)a.F + D.oF;
+  fv.fs = stage_factor_elems(D.nx, D.nu);
+  fv.nx = D.nx; fv.nu = D.nu;
+  const int N = D.N, nx = D.nx, nu = D.nu;
+  const double* rb0 = a.V + D.oV;
+  const double* p0 = rb0 + (int64_t)N * nu;
+  double* rb2 = a.V2 + D.oV2;
+  double* p2 = rb2 + (int64_t)N * nu;
+  double* flam = p2 + (int64_t)(N + 1) * nx;
+
+  if (a.rhs == RHS_PRIMAL) {
+    fwd_sweep<TF>(v, fv, rb0, p0, nullptr, 0, sm);
+  } else {
+    // adjoint: backward sweep of (r, q, f) = (-gu, -gx, 0) first (lq_factor did the primal one)
+    // The residual pass of the zero iterate gives exactly -rho = the right-hand side, so the
+    // iterate is zeroed and one residual/sweep pass plus a forward correction gives zbar.
+    for (int k = 0; k < N; ++k) {
+      for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        v.x[(int64_t)k * nx + i] = 0.0;
+        v.lam[(int64_t)k * nx + i] = 0.0;
+      }
+      for (int i = threadIdx.x; i < nu; i += blockDim.x) v.u[(int64_t)k * nu + i] = 0.0;
+    }
+    __syncthreads();
+    resid_bwd<TF>(v, fv, true, rb2, p2, flam, sm, red);
+    fwd_sweep<TF>(v, fv, rb2, p2, flam, 1, sm);
+  }
+  int it = 0;
+  double rel = 0.0;
+  bool have = false;
+  if (a.check || a.max_it > 0) {
+    for (;;) {
+      const bool more = it < a.max_it;
+      rel = resid_bwd<TF>(v, fv, more, rb2, p2, flam, sm, red);
+      have = true;
+      if (!(rel > a.tol) || !more) break;  // converged (or NaN handled below) or out of iterations
+      fwd_sweep<TF>(v, fv, rb2, p2, flam, 1, sm);
+      ++it;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (a.rel_res) a.rel_res[b] = have ? rel : NAN;
+    if (a.iters) a.iters[b] = it;
+    if (a.info) {
+      int cur = a.info[b];
+      if (cur <= 0) {
+        int code = 0;
+        if (have && !isfinite(rel)) code = LQ_INFO_NONFINITE;
+        else if (have && a.max_it > 0 && rel > a.tol) code = LQ_INFO_NOT_CONVERGED;
+        else if (cur == LQ_INFO_NONFINITE) code = cur;
+        a.info[b] = code;
+      }
+    }
+  }
+}
+
+// Gradient outer products of the adjoint (one workgroup per instance).
+
+__global__ void __launch_bounds__(128) k_grad_generic(GradArgs a) {
+  const int b = blockIdx.x;
+  if (b >= a.batch) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* x = a.x + D.ox;
+  const double* u = a.u + D.ou;
+  const double* lam = a.lam + D.olam;
+  const double* xb = a.ZB + D.oZB;
+  const double* ub = xb + (int64_t)N * nx;
+  const double* lb = ub + (int64_t)N * nu;
+  const double* x0 = a.d.x0 + D.ox0;
+#define XS(k, i) ((k) == 0 ? x0[i] : x[(int64_t)((k)-1) * nx + (i)])
+#define XB(k, i) ((k) == 0 ? 0.0 : xb[(int64_t)((k)-1) * nx + (i)])
+  for (int k = 0; k < N; ++k) {
+    double* gA = a.gA + D.oA + (int64_t)k * nx * nx;
+    for (int e = tid; e < nx * nx; e += nt) {
+      const int i = e / nx, j = e % nx;
+      gA[e] = -(lb[(int64_t)k * nx + i] * XS(k, j) + lam[(int64_t)k * nx + i] * XB(k, j));
+    }
+    double* gB = a.gB + D.oB + (int64_t)k * nx * nu;
+    for (int e = tid; e < nx * nu; e += nt) {
+      const int i = e / nu, j = e % nu;
+      gB[e] = -(lb[(int64_t)k * nx + i] * u[(int64_t)k * nu + j] + lam[(int64_t)k * nx + i] * ub[(int64_t)k * nu + j]);
+    }
+    double* gR = a.gR + D.oR + (int64_t)k * nu * nu;
+    for (int e = tid; e < nu * nu; e += nt) {
+      const int i = e / nu, j = e % nu;
+      gR[e] = -0.5 * (ub[(int64_t)k * nu + i] * u[(int64_t)k * nu + j] + u[(int64_t)k * nu + i] * ub[(int64_t)k * nu + j]);
+    }
+    if (a.gS) {
+      double* gS = a.gS + D.oS + (int64_t)k * nu * nx;
+      for (int e = tid; e < nu * nx; e += nt) {
+        const int i = e / nx, j = e % nx;
+        gS[e] = -(ub[(int64_t)k * nu + i] * XS(k, j) + u[(int64_t)k * nu + i] * XB(k, j));
+      }
+    }
+    for (int j = tid; j < nu; j += nt) a.gr[D.or_ + (int64_t)k * nu + j] = -ub[(int64_t)k * nu + j];
+    if (a.gf)
+      for (int i = tid; i < nx; i += nt) a.gf[D.of + (int64_t)k * nx + i] = -lb[(int64_t)k * nx + i];
+  }
+  for (int k = 0; k <= N; ++k) {
+    double* gQ = a.gQ + D.oQ + (int64_t)k * nx * nx;
+    for (int e = tid; e < nx * nx; e += nt) {
+      const int i = e / nx, j = e % nx;
+      gQ[e] = k == 0 ? 0.0 : -0.5 * (XB(k, i) * XS(k, j) + XS(k, i) * XB(k, j));
+    }
+    for (int i = tid; i < nx; i += nt) a.gq[D.oq + (int64_t)k * nx + i] = k == 0 ? 0.0 : -XB(k, i);
+  }
+  const double* A0 = a.d.A + D.oA;
+  const double* S0 = a.d.S ? a.d.S + D.oS : nullptr;
+  for (int j = tid; j < nx; j += nt) {
+    double s = 0.0;
+    for (int i = 0; i < nx; ++i) s += A0[i * nx + j] * lb[i];
+    if (S0)
+      for (int i = 0; i < nu; ++i) s += S0[i * nx + j] * ub[i];
+    a.gx0[D.ox0 + j] = -s;
+  }
+#undef XS
+#undef XB
+}
+
+// ------------------------------------------------------------------------------------------
+// Host-side launchers (called from the runtime).
+
+size_t generic_factor_lds(int nx, int nu) {
+  const int nux = nx + nu;
+  return sizeof(double) * ((size_t)nux * nux + (size_t)nx * nx + (size_t)nux * nx + 3 * nx + 2 * nux);
+}
+size_t generic_solve_lds(int nx, int nu) { return sizeof(double) * (size_t)(7 * nx + 3 * nu + nx + nu); }
+
+hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F,
+                                 double* V, int32_t* info, size_t lds, hipStream_t st) {
+  if (mode == LQ_F64) {
+    auto k = k_factor_generic<double, double>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(batch), dim3(128), lds, st, desc, batch, d, (double*)F, V, info);
+  } else {
+    auto k = k_factor_generic<float, float>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(batch), dim3(128), lds, st, desc, batch, d, (float*)F, V, info);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, hipStream_t st) {
+  if (mode == LQ_F64) {
+    hipLaunchKernelGGL(k_solve_generic<double>, dim3(a.batch), dim3(128), lds, st, a, (int64_t)0);
+  } else {
+    hipLaunchKernelGGL(k_solve_generic<float>, dim3(a.batch), dim3(128), lds, st, a, (int64_t)0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_generic(const GradArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_generic, dim3(a.batch), dim3(128), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace lq

@@ -1,0 +1,70 @@
+// Internal definitions shared by the host runtime and the kernels of liblqkkt.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lqkkt.h"
+
+namespace lq {
+
+// Per-instance descriptor: sizes and element offsets into the packed input, output and
+// workspace arrays.  Built on the host by the plan, read once per instance by the kernels.
+struct Desc {
+  int32_t N, nx, nu, pad;
+  int64_t oA, oB, oQ, oR, oS, oq, or_, of, ox0;  // inputs
+  int64_t ox, ou, olam;                           // outputs (x_1..x_N, u_0..u_{N-1}, lam)
+  int64_t oF;   // factor region (elements of the factor type)
+  int64_t oV;   // rbar (N nu) then p ((N+1) nx), float64: sweep of lq_factor's right-hand side
+  int64_t oV2;  // same shape: sweeps of refinement corrections and of the adjoint
+  int64_t oZB;  // adjoint solution: xbar (N nx), ubar (N nu), lambar (N nx), float64
+};
+
+// Factor block of one stage (elements): [LR packed lower, nu(nu+1)/2][1/diag LR, nu]
+// [LS, nx*nu row-major][LQ packed lower, nx(nx+1)/2][1/diag LQ, nx].  Stage N holds only
+// the LQ part (chol Q_N); stage 0 leaves the LQ part unused.
+__host__ __device__ inline int64_t stage_factor_elems(int nx, int nu) {
+  return (int64_t)nu * (nu + 1) / 2 + nu + (int64_t)nx * nu + (int64_t)nx * (nx + 1) / 2 + nx;
+}
+__host__ __device__ inline int off_dR(int nx, int nu) { return nu * (nu + 1) / 2; }
+__host__ __device__ inline int off_LS(int nx, int nu) { return nu * (nu + 1) / 2 + nu; }
+__host__ __device__ inline int off_LQ(int nx, int nu) { return nu * (nu + 1) / 2 + nu + nx * nu; }
+__host__ __device__ inline int off_dQ(int nx, int nu) {
+  return nu * (nu + 1) / 2 + nu + nx * nu + nx * (nx + 1) / 2;
+}
+
+// Right-hand side selector of the solve kernels.
+enum RhsKind : int32_t { RHS_PRIMAL = 0, RHS_ADJOINT = 1 };
+
+struct SolveArgs {
+  const Desc* desc;
+  int32_t batch;
+  lq_data d;
+  const void* F;       // factors (double or float)
+  const double* V;     // factor-time right-hand-side sweep (rbar, p)
+  double* V2;          // correction sweeps
+  double* x;           // solution being refined (primal x/u/lam or adjoint xbar/ubar/lambar)
+  double* u;
+  double* lam;
+  const double* gx;    // adjoint right-hand side (RHS_ADJOINT)
+  const double* gu;
+  double tol;
+  int32_t max_it;
+  int32_t check;
+  int32_t rhs;         // RhsKind
+  int32_t out_is_zb;   // 1: x/u/lam point into the workspace adjoint region (per-instance oZB)
+  double* rel_res;
+  int32_t* iters;
+  int32_t* info;
+};
+
+// Gradient outer products of the adjoint.
+struct GradArgs {
+  const Desc* desc;
+  int32_t batch;
+  lq_data d;
+  const double *x, *u, *lam;  // primal solution
+  const double* ZB;           // adjoint solution region (workspace)
+  double *gA, *gB, *gQ, *gR, *gS, *gq, *gr, *gf, *gx0;
+};
+
+}  // namespace lq

@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point include/lqkkt.h declares; host-side
+argument validation (no GPU needed: it returns before any HIP call)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2512_09058_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lqkkt.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lq_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_three_entry_points():
+    names = declared_functions()
+    for n in ("lq_factor", "lq_solve", "lq_solve_backward"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_version_and_error_string():
+    lib = _lib.load()
+    assert lib.lq_version() == 100
+    assert lib.lq_last_error() == b""
+
+
+def _create(batch, N, nx, nu, mode=0, ckpt=0, out=True):
+    lib = _lib.load()
+    arr = lambda v: (C.c_int32 * max(batch, 1))(*([v] * max(batch, 1)))  # noqa: E731
+    h = C.c_void_p()
+    return lib.lq_plan_create(batch, arr(N), arr(nx), arr(nu), mode, ckpt, C.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 10, 2, 1), _lib.LQ_EINVAL),
+    ((-3, 10, 2, 1), _lib.LQ_EINVAL),
+    ((2, 0, 2, 1), _lib.LQ_EINVAL),
+    ((2, 10, -1, 1), _lib.LQ_EINVAL),
+    ((2, 10, 2, 0), _lib.LQ_EINVAL),
+])
+def test_plan_rejects_bad_sizes(args, code):
+    assert _create(*args) == code
+    assert b"lq_plan_create" in _lib.load().lq_last_error()
+
+
+def test_plan_rejects_bad_mode_and_stride_and_null_out():
+    assert _create(2, 10, 2, 1, mode=7) == _lib.LQ_EINVAL
+    assert _create(2, 10, 2, 1, ckpt=-1) == _lib.LQ_EINVAL
+    assert _create(2, 10, 2, 1, out=False) == _lib.LQ_EINVAL
+
+
+def test_calls_reject_null_plan():
+    lib = _lib.load()
+    d = _lib.LqData()
+    assert lib.lq_factor(None, C.byref(d), None, None, None) == _lib.LQ_EINVAL
+    o = _lib.LqSolveOpts(1e-10, 0, 1)
+    assert lib.lq_solve(None, C.byref(d), None, C.byref(o), *([None] * 7)) == _lib.LQ_EINVAL
+    assert lib.lq_solve_backward(None, C.byref(d), None, C.byref(o), *([None] * 18)) == _lib.LQ_EINVAL
+    assert lib.lq_plan_workspace_bytes(None) == 0
+    assert lib.lq_plan_offsets(None, 0, None) == -1

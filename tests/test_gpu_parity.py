@@ -1,0 +1,131 @@
+"""Parity of the HIP path with the CPU oracle (float64 and mixed precision).
+
+Bar (stated per case): relative KKT residual rel_res = ||b - K z||_inf / ||b||_inf of the GPU
+solution <= 1e-10, computed both by the library (float64) and by the oracle's own residual
+routine; forward error against the oracle's direct solve <= 1e-9 (relative, inf-norm), which
+the condition numbers of these problems (<= ~1e5) allow after a 1e-10 residual... plus the
+factor comparisons.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kkt, riccati
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from gpu_util import forward_error, instance_solution, oracle_solution, run  # noqa: E402
+
+
+def _check(res, tol_res=1e-10, tol_fwd=1e-9, sample=None):
+    insts = res["insts"]
+    idx = range(len(insts)) if sample is None else sample
+    assert np.all(res["info"] == 0), res["info"]
+    assert np.all(res["rel"] <= tol_res), res["rel"].max()
+    for i in idx:
+        p = insts[i]
+        sol = instance_solution(res, i)
+        _, rel_o = kkt.residual(p, *sol)
+        assert rel_o <= tol_res, (i, rel_o)
+        assert forward_error(sol, oracle_solution(p)) <= tol_fwd, i
+
+
+def test_config1_single_problem_f64():
+    p = synth.make_instance(1, 0)
+    print("case: config-1 instance 0, f64", flush=True)
+    _check(run([p], "f64"))
+
+
+@pytest.mark.parametrize("N,nx,nu", [(1, 1, 1), (1, 3, 2), (2, 1, 1), (3, 5, 1), (7, 4, 3), (16, 12, 4),
+                                     (9, 33, 7), (5, 64, 16), (4, 17, 31)])
+def test_random_with_S_and_f(N, nx, nu):
+    print(f"case: random N={N} nx={nx} nu={nu}", flush=True)
+    b = synth.random_problem(1000 + N + nx + nu, N, nx, nu, batch=3)
+    _check(run(b, "f64"))
+
+
+def test_ragged_batch_f64():
+    insts = [synth.random_problem(50 + i, N, nx, nu) for i, (N, nx, nu) in
+             enumerate([(3, 2, 1), (20, 12, 4), (1, 1, 1), (8, 31, 9), (12, 6, 16)])]
+    print("case: ragged random f64", flush=True)
+    _check(run(insts, "f64"))
+
+
+def test_config2_reduced_f64():
+    print("case: config-2 batch 64 f64", flush=True)
+    _check(run(synth.make_batch(2, batch=64), "f64"))
+
+
+def test_config2_reduced_mixed_f32_refined():
+    print("case: config-2 batch 64 mixed_f32 refined", flush=True)
+    res = run(synth.make_batch(2, batch=64), "mixed_f32", max_it=10)
+    _check(res)
+    assert res["iters"].max() <= 3
+
+
+def test_mixed_without_refinement_meets_f32_bound():
+    print("case: config-2 batch 16 mixed_f32 unrefined", flush=True)
+    res = run(synth.make_batch(2, batch=16), "mixed_f32", max_it=0)
+    assert np.all(res["rel"] <= 1e-3)
+    assert np.all(res["rel"] > 1e-14)
+
+
+def test_factors_match_oracle_cost_to_go():
+    from paper_2512_09058_amd import api
+    p = synth.random_problem(77, 6, 5, 3)
+    res = run([p], "f64")
+    ws = res["ws"].cpu().numpy().view(np.float64)
+    nx, nu, N = p.nx, p.nu, p.N
+    fs = nu * (nu + 1) // 2 + nu + nx * nu + nx * (nx + 1) // 2 + nx
+    LQ, LR, LS = riccati.reference_factors(p)
+
+    def tri(v, n):
+        M = np.zeros((n, n))
+        M[np.tril_indices(n)] = v
+        return M
+
+    for k in range(N + 1):
+        blk = ws[k * fs:(k + 1) * fs]
+        o = 0
+        Lr = tri(blk[o:o + nu * (nu + 1) // 2], nu); o += nu * (nu + 1) // 2
+        dR = blk[o:o + nu]; o += nu
+        Ls = blk[o:o + nx * nu].reshape(nx, nu); o += nx * nu
+        Lq = tri(blk[o:o + nx * (nx + 1) // 2], nx); o += nx * (nx + 1) // 2
+        dQ = blk[o:o + nx]
+        if k >= 1:
+            np.testing.assert_allclose(Lq, LQ[k], rtol=0, atol=1e-12 * np.abs(LQ[k]).max())
+            np.testing.assert_allclose(dQ, 1 / np.diag(LQ[k]), rtol=1e-13)
+        if k < N:
+            np.testing.assert_allclose(Lr, LR[k], rtol=0, atol=1e-12 * np.abs(LR[k]).max())
+            np.testing.assert_allclose(Ls, LS[k], rtol=0, atol=1e-12 * max(1, np.abs(LS[k]).max()))
+            np.testing.assert_allclose(dR, 1 / np.diag(LR[k]), rtol=1e-13)
+
+
+def test_indefinite_stage_reports_info():
+    p = synth.random_problem(5, 6, 3, 2)
+    p.R[3] = -np.eye(2) * 50.0  # R_3 strongly indefinite -> stage 3 not positive definite
+    q = synth.random_problem(6, 6, 3, 2)
+    print("case: indefinite R_3", flush=True)
+    res = run([p, q], "f64", max_it=0)
+    assert res["info"][0] == 4
+    assert res["info"][1] == 0
+
+
+def test_nonfinite_input_reports_info():
+    p = synth.random_problem(9, 5, 3, 2)
+    p.A[2, 1, 1] = np.nan
+    print("case: NaN in A_2", flush=True)
+    res = run([p, synth.random_problem(10, 5, 3, 2)], "f64", max_it=0)
+    assert res["info"][0] == -1
+    assert res["info"][1] == 0
+
+
+def test_refinement_not_converged_reports_info():
+    print("case: mixed, max_it=1, tol=1e-30", flush=True)
+    res = run(synth.make_batch(2, batch=4), "mixed_f32", tol=1e-30, max_it=1)
+    assert np.all(res["info"] == -2)
+    assert np.all(res["iters"] == 1)

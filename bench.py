@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark: batched LQ KKT solves/s on one MI355X, mixed precision vs float64 at equal residual.
+
+Workload (the metric's configuration): 4096 independent time-varying LQ problems, N = 50,
+nx = 12, nu = 4, synthetic seeded inputs (A = I + 0.05 G, B = 0.5 G, Q = M M^T + 0.1 I,
+R = 0.1 I + diag(U(0,1)), q, r, x0 ~ N(0,1)), resident in HBM before timing.
+
+One step = lq_factor + lq_solve for the whole batch (factor sweep, right-hand-side sweeps,
+forward rollout, float64 KKT residual of every instance, refinement).  Both paths must reach
+max rel_res <= 1e-10 (the float64 path certifies with one residual pass, the mixed path refines
+until it gets there).  `value` is the mixed path's solves/s; the float64 path is reported beside
+it.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LQ KKT solves/s, batch 4096 nx=12 nu=4 N=50: mixed vs FP64 at equal residual"
+BATCH, N, NX, NU = 4096, 50, 12, 4
+TOL = 1e-10
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_factor(batch, N, nx, nu, fbytes):
+    """Minimum HBM bytes of the factor sweep: read A, B, Q_1..Q_N, R, q_1..q_N, r once; write the
+    packed factors (L^R, L^S, L^Q lower triangles + inverse diagonals) in the storage precision and
+    the float64 backward-sweep vectors rbar_k, p_k."""
+    per_stage_in = 8 * (nx * nx + nx * nu + nx * nx + nu * nu + nx + nu)
+    fac = nu * (nu + 1) // 2 + nu + nx * nu + nx * (nx + 1) // 2 + nx
+    per_stage_out = fbytes * fac + 8 * (nu + nx)
+    return batch * N * (per_stage_in + per_stage_out)
+
+
+def algorithmic_bytes_solve(batch, N, nx, nu, fbytes, passes_fwd, passes_res):
+    """Minimum HBM bytes of lq_solve: each forward pass reads the factors, rbar/p, A_k, B_k and
+    writes x, u, lam; each residual pass reads all stage data and the iterate."""
+    fac = fbytes * (nu * (nu + 1) // 2 + nu + nx * nu + nx * (nx + 1) // 2 + nx)
+    z = 8 * (2 * nx + nu)
+    fwd = fac + 8 * (nu + nx) + 8 * (nx * nx + nx * nu) + z
+    res = 8 * (nx * nx + nx * nu + nx * nx + nu * nu + nx + nu) + z
+    return batch * N * (passes_fwd * fwd + passes_res * res)
+
+
+def oracle_worker(args):
+    import synth
+    from oracle import riccati
+    start, count = args
+    probs = [synth.make_instance(2, i) for i in range(start, start + count)]
+    t0 = time.perf_counter()
+    for p in probs:
+        riccati.solve(p)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(sample=2048, workers=None):
+    """The oracle's textbook Riccati route (numpy float64) over a sample of the workload: each
+    process generates its instances, then times their solves; throughput = sample / slowest
+    process's solve time."""
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    workers = workers or min(os.cpu_count() or 1, 16)
+    per = max(1, sample // workers)
+    jobs = [(w * per, per) for w in range(workers)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        times = pool.map(oracle_worker, jobs)
+    n = per * workers
+    t = max(times)
+    return {"value": n / t, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n} instances of the workload (same generator), textbook Riccati route "
+                      f"(numpy float64, 1 BLAS thread per process), {workers} processes, slowest {t:.1f} s"}
+
+
+def run_path(mode, data, steps, warmup, max_it):
+    import torch
+    import paper_2512_09058_amd as L
+    plan = L.Plan(N, NX, NU, batch=BATCH, mode=mode)
+    ws = plan.workspace()
+    info = torch.zeros(BATCH, dtype=torch.int32, device="cuda")
+    rel = torch.zeros(BATCH, dtype=torch.float64, device="cuda")
+    its = torch.zeros(BATCH, dtype=torch.int32, device="cuda")
+    x, u, lam = plan.empty_outputs()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        L.factor(plan, data, ws, info, stream=stream)
+        L.solve(plan, data, ws, x, u, lam, rel, its, info, tol=TOL, max_it=max_it, check_res=True, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-kernel durations with HIP events on the stream the library launches on
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for s in range(steps):
+        ev[s][0].record(stream)
+        L.factor(plan, data, ws, info, stream=stream)
+        ev[s][1].record(stream)
+        L.solve(plan, data, ws, x, u, lam, rel, its, info, tol=TOL, max_it=max_it, check_res=True, stream=stream)
+        ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    tf = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    ts = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    return {"plan": plan, "ms_per_step": 1e3 * wall / steps, "ms_factor": tf, "ms_solve": ts,
+            "rel": rel.cpu().numpy(), "iters": its.cpu().numpy(), "info": info.cpu().numpy(),
+            "x": x, "u": u, "lam": lam}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-it", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the instances of the batch are "
+              "independent, so more GPUs would each run this same kernel on their own share; no multi-GPU run "
+              "is built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    from oracle import kkt
+
+    t0 = time.perf_counter()
+    prob = synth.make_batch(2)
+    data = L.pack(prob)
+    torch.cuda.synchronize()
+    print(f"[bench] generated and uploaded workload in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    res = {}
+    for mode, max_it in (("f64", 0), ("mixed_f32", args.max_it)):
+        r = run_path(mode, data, args.steps, args.warmup, max_it)
+        res[mode] = r
+        print(f"[bench] {mode}: {r['ms_per_step']:.3f} ms/step (factor {r['ms_factor']:.3f} ms, solve "
+              f"{r['ms_solve']:.3f} ms), max rel_res {r['rel'].max():.2e}, iters max {r['iters'].max()}, "
+              f"variant {r['plan'].variant}", file=sys.stderr, flush=True)
+
+    # sampled cross-check with the oracle's own residual routine
+    sample = [0, 1, 777, 2048, 4095]
+    worst = {}
+    for mode, r in res.items():
+        w = 0.0
+        for i in sample:
+            sol = [L.unpack(r["plan"], n, r[n], i) for n in ("x", "u", "lam")]
+            w = max(w, kkt.residual(prob.instance(i), *sol)[1])
+        worst[mode] = w
+
+    m, f = res["mixed_f32"], res["f64"]
+    ok = all(np.all(r["info"] == 0) and r["rel"].max() <= TOL for r in res.values())
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_sample)
+
+    # roofline of the dominant kernel of the reported (mixed) path
+    it_mean = float(np.mean(m["iters"]))
+    passes_fwd = 1 + int(m["iters"].max())
+    passes_res = 1 + int(m["iters"].max())
+    kern = {"factor": (m["ms_factor"], algorithmic_bytes_factor(BATCH, N, NX, NU, 4)),
+            "solve": (m["ms_solve"], algorithmic_bytes_solve(BATCH, N, NX, NU, 4, passes_fwd, passes_res))}
+    dom = max(kern, key=lambda k: kern[k][0])
+    ms, by = kern[dom]
+    achieved = by / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": BATCH / (m["ms_per_step"] * 1e-3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 stage products + f64 Cholesky/residual/refinement",
+        "data": "synthetic (seeded generators of the workload)",
+        "config": {"workload": "batch 4096 LQ problems, N=50, nx=12, nu=4 (mixed f32 + f64 refinement)",
+                   "batch": BATCH, "N": N, "nx": NX, "nu": NU, "tol": TOL, "max_it": args.max_it,
+                   "variant": m["plan"].variant},
+        "fp64": {"value": BATCH / (f["ms_per_step"] * 1e-3), "ms_per_step": f["ms_per_step"],
+                 "ms_factor": f["ms_factor"], "ms_solve": f["ms_solve"], "max_rel_res": float(f["rel"].max()),
+                 "oracle_rel_res_sampled": worst["f64"]},
+        "mixed": {"ms_factor": m["ms_factor"], "ms_solve": m["ms_solve"], "max_rel_res": float(m["rel"].max()),
+                  "iters_mean": it_mean, "iters_max": int(m["iters"].max()),
+                  "oracle_rel_res_sampled": worst["mixed_f32"]},
+        "mixed_over_fp64": f["ms_per_step"] / m["ms_per_step"],
+        "equal_residual_ok": bool(ok),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": by, "ms_per_launch": ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -129,3 +129,42 @@ def test_refinement_not_converged_reports_info():
     res = run(synth.make_batch(2, batch=4), "mixed_f32", tol=1e-30, max_it=1)
     assert np.all(res["info"] == -2)
     assert np.all(res["iters"] == 1)
+
+
+SMALL_SHAPES = [(12, 4), (4, 2), (8, 4), (10, 6), (6, 2)]
+
+
+@pytest.mark.parametrize("nx,nu", SMALL_SHAPES)
+@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 6)])
+def test_small_variant_with_S_and_f(nx, nu, mode, max_it):
+    """Uniform batches of the size-specialised shapes (16 lanes per instance); batch 9 leaves a
+    partly empty last wavefront."""
+    print(f"case: small nx={nx} nu={nu} {mode}", flush=True)
+    b = synth.random_problem(300 + nx * 7 + nu, 11, nx, nu, batch=9)
+    res = run(b, mode, max_it=max_it)
+    assert res["plan"].variant == "small"
+    _check(res)
+
+
+def test_small_variant_config2_batch_and_tail():
+    print("case: config-2 batch 130 small f64 + mixed", flush=True)
+    b = synth.make_batch(2, batch=130)
+    r64 = run(b, "f64")
+    assert r64["plan"].variant == "small"
+    _check(r64, sample=[0, 1, 64, 127, 128, 129])
+    rmx = run(b, "mixed_f32", max_it=6)
+    _check(rmx, sample=[0, 129])
+
+
+def test_small_and_generic_agree():
+    """Same instances through the specialised and the generic kernels (the generic one is forced
+    by a ragged plan that appends one differently sized instance)."""
+    b = synth.make_batch(2, batch=8, N=20)
+    extra = synth.random_problem(1, 3, 2, 1)
+    rs = run(b, "f64")
+    rg = run([b.instance(i) for i in range(8)] + [extra], "f64")
+    assert rs["plan"].variant == "small" and rg["plan"].variant == "generic"
+    for i in range(8):
+        a = instance_solution(rs, i)
+        g = instance_solution(rg, i)
+        assert forward_error(a, g) <= 1e-12

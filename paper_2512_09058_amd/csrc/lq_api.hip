@@ -125,7 +125,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     D.ox = p->off[LQ_ARR_x][i]; D.ou = p->off[LQ_ARR_u][i]; D.olam = p->off[LQ_ARR_lam][i];
     D.oF = aF; aF += (n + 1) * lq::stage_factor_elems(nx[i], nu[i]);
     D.oV = aV; aV += n * u + (n + 1) * x;
-    D.oV2 = aV2; aV2 += n * u + (n + 1) * x + n * x;
+    D.oV2 = aV2; aV2 += lq::v2_elems(n, x, u);
     D.oZB = aZB; aZB += n * (2 * x + u);
     ldsf = std::max(ldsf, lq::generic_factor_lds(nx[i], nu[i]));
     ldss = std::max(ldss, lq::generic_solve_lds(nx[i], nu[i]));

@@ -15,7 +15,7 @@ struct Desc {
   int64_t ox, ou, olam;                           // outputs (x_1..x_N, u_0..u_{N-1}, lam)
   int64_t oF;   // factor region (elements of the factor type)
   int64_t oV;   // rbar (N nu) then p ((N+1) nx), float64: sweep of lq_factor's right-hand side
-  int64_t oV2;  // same shape: sweeps of refinement corrections and of the adjoint
+  int64_t oV2;  // refinement / adjoint state, float64 (layout: v2_* below)
   int64_t oZB;  // adjoint solution: xbar (N nx), ubar (N nu), lambar (N nx), float64
 };
 
@@ -30,6 +30,18 @@ __host__ __device__ inline int off_LS(int nx, int nu) { return nu * (nu + 1) / 2
 __host__ __device__ inline int off_LQ(int nx, int nu) { return nu * (nu + 1) / 2 + nu + nx * nu; }
 __host__ __device__ inline int off_dQ(int nx, int nu) {
   return nu * (nu + 1) / 2 + nu + nx * nu + nx * (nx + 1) / 2;
+}
+
+// Refinement state of one instance (float64): rbar2 [N nu] | p2 [(N+1) nx] | flam [N nx]
+// (= -rho_l, the dynamics residual) | rho_u [N nu] | rho_x [(N+1) nx] (k = 1..N used).
+__host__ __device__ inline int64_t v2_elems(int64_t N, int64_t nx, int64_t nu) {
+  return 2 * N * nu + 2 * (N + 1) * nx + N * nx;
+}
+__host__ __device__ inline int64_t v2_p2(int64_t N, int64_t nx, int64_t nu) { return N * nu; }
+__host__ __device__ inline int64_t v2_flam(int64_t N, int64_t nx, int64_t nu) { return N * nu + (N + 1) * nx; }
+__host__ __device__ inline int64_t v2_rhou(int64_t N, int64_t nx, int64_t nu) { return N * nu + (N + 1) * nx + N * nx; }
+__host__ __device__ inline int64_t v2_rhox(int64_t N, int64_t nx, int64_t nu) {
+  return 2 * N * nu + (N + 1) * nx + N * nx;
 }
 
 // Right-hand side selector of the solve kernels.

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "liblqkkt.so")
 ARCH = os.environ.get("LQKKT_ARCH", "gfx950")
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=fast",
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=fast", "-fno-strict-aliasing",
     # packed FP32 VALU instructions stay disabled in all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-command-line-argument",

@@ -20,6 +20,7 @@ hipError_t launch_grad_generic(const GradArgs& a, hipStream_t st);
 
 // Size-specialised uniform-batch kernels (lq_small.hip); return false if no variant fits.
 bool small_variant_available(lq_mode mode, int nx, int nu);
+bool small_aligned(const lq_data& d, const void* ws);
 hipError_t launch_factor_small(lq_mode mode, int batch, int N, int nx, int nu, const lq_data& d,
                                void* F, double* V, int32_t* info, hipStream_t st);
 hipError_t launch_solve_small(lq_mode mode, int N, int nx, int nu, const SolveArgs& a, hipStream_t st);
@@ -210,7 +211,7 @@ extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* 
   void* F = w + p->offF;
   double* V = (double*)(w + p->offV);
   hipError_t e;
-  if (p->variant == VAR_SMALL)
+  if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_factor_small(p->mode, p->batch, p->N[0], p->nx[0], p->nu[0], *d, F, V, info, st);
   else
     e = lq::launch_factor_generic(p->mode, p->desc_d, p->batch, *d, F, V, info, p->lds_factor, st);
@@ -254,7 +255,7 @@ extern "C" int lq_solve(const lq_plan* p, const lq_data* d, void* ws, const lq_s
   a.rhs = lq::RHS_PRIMAL;
   a.rel_res = rel_res; a.iters = iters; a.info = info;
   hipError_t e;
-  if (p->variant == VAR_SMALL)
+  if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_solve_small(p->mode, p->N[0], p->nx[0], p->nu[0], a, st);
   else
     e = lq::launch_solve_generic(p->mode, a, p->lds_solve, st);

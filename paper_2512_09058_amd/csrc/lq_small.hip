@@ -1,17 +1,21 @@
 // Size-specialised kernels for uniform batches with nx + nu <= 16.
 //
-// Mapping: 16 lanes per instance, four instances per 64-wide wavefront.  Lane i of an
-// instance owns row i of the stage matrix Hhat_k = [[R,S],[S^T,Q]] + V V^T (rows 0..nu-1 are
-// the inputs, rows nu..nu+nx-1 the states) and, after the stage Cholesky, row i of its factor
-// [[L^R, 0],[L^S, L^Q]].  What an instance carries from stage to stage (rows of L^Q_{k+1},
-// p_{k+1}; in the solve, x_k and lam_{k-1}) stays in registers.  Cross-row operands are
-// broadcast inside the 16-lane row with 64-bit DPP row_newbcast moves (VALU, no LDS).
+// Mapping: 16 lanes per instance, four instances per 64-wide wavefront (one wavefront per
+// workgroup).  Lane i of an instance owns row i of the stage matrix
+// Hhat_k = [[R,S],[S^T,Q]] + V V^T (rows 0..nu-1: inputs, rows nu..nu+nx-1: states) and, after
+// the stage Cholesky, row i of its factor [[L^R, 0],[L^S, L^Q]].  What an instance carries from
+// stage to stage (rows of L^Q_{k+1}, p_{k+1}; in the solve, x_k and lam_{k-1}) stays in
+// registers.  Cross-row operands are broadcast inside the 16-lane row with 64-bit DPP
+// row_newbcast moves.
 //
-// With one wavefront per SIMD (4096 instances = 1024 wavefronts), latency is hidden by
-// instruction-level parallelism only, so all global loads use per-lane clamped addresses
-// (no branches around them) and the loads of stage k-1 are issued before stage k is computed.
+// Memory: each stage's matrices of the four instances are fetched with coalesced 16-byte loads
+// one stage ahead (they do not depend on the recursion), written to LDS laid out as
+// C = [B_k A_k] (nx rows of nu+nx) and H = [[R_k, S_k], [., Q_k]], and read back per lane as
+// rows or columns at compile-time offsets.  Factor blocks leave through LDS as coalesced
+// 16-byte stores.  (Reading rows per lane straight from global memory touches a different
+// cache line per lane and leaves the kernel bound by the vector-memory pipeline.)
 //
-// Factor sweep per stage (backward in time), c_i = column i of [B_k A_k] in lane i:
+// Factor sweep per stage (backward in time), c_i = column i of C held by lane i:
 //   V[i][j]    = sum_{m>=j} c_i[m] L^Q_{k+1}[m][j]       (trmm: broadcast rows of L^Q)
 //   Hhat[i][j] = H[i][j] + sum_m V[i][m] V[j][m]          (syrk: broadcast rows of V)
 //   chol(Hhat)                                            (potrf, float64, right-looking)
@@ -20,16 +24,23 @@
 //
 // Solve: one forward pass computes the rollout and, in the same pass, the float64 KKT
 // residual of the new iterate (eq. opt-cond-ocp-eq); each refinement iteration is a backward
-// correction sweep over the stored residual followed by another forward+residual pass.
+// correction sweep over the stored residual followed by another forward+residual pass.  The
+// four instances of a wavefront share the LDS staging, so they run every pass together; an
+// instance that has converged runs it with its stores masked.
 //
 // Factor blocks use the generic workspace layout, so the generic solve and adjoint kernels
 // consume these factors unchanged.
 #include <math.h>
 
+#include <type_traits>
+
 #include "lq_internal.hpp"
 
 namespace lq {
 namespace {
+
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double rsqrt_f64(double a) {
   double y = __builtin_amdgcn_rsq(a);
@@ -82,25 +93,25 @@ __device__ __forceinline__ double rowmax(double v) {
 }
 
 // Right-looking Cholesky of the row-distributed tile (lane i holds row i in h), pivot
-// columns 0..NCOL-1.  Returns 0, 1 (a pivot was not positive) or 2 (non-finite pivot); bad
-// pivots are replaced by 1 so the sweep continues without NaNs.
+// columns 0..NCOL-1.  Returns 0, 1 (a pivot was not positive) or 2 (a pivot was not finite);
+// failed pivots are replaced by 1 so the sweep continues with finite numbers.
 template <int NUX, int NCOL>
 __device__ __forceinline__ int potrf_rows(double (&h)[NUX], double& mydinv, int i) {
-  int bad = 0;
+  bool ok = true, fin = true;
 #pragma unroll
   for (int j = 0; j < NCOL; ++j) {
     double dj = bc(h[j], j);
-    const bool fin = isfinite(dj);
-    const bool ok = fin && dj > 0.0;
-    bad = (bad == 0 && !ok) ? (fin ? 1 : 2) : bad;
-    dj = ok ? dj : 1.0;
+    const bool pos = dj > 0.0;
+    ok = ok && pos;
+    fin = fin && isfinite(dj);
+    dj = pos ? dj : 1.0;
     const double inv = rsqrt_f64(dj);
     h[j] = (i == j) ? dj * inv : h[j] * inv;
     mydinv = (i == j) ? inv : mydinv;
 #pragma unroll
     for (int kk = j + 1; kk < NCOL; ++kk) h[kk] = fma(-h[j], bc(h[j], kk), h[kk]);
   }
-  return bad;
+  return ok ? 0 : (fin ? 1 : 2);
 }
 
 template <typename T>
@@ -111,26 +122,31 @@ __device__ __forceinline__ double rnd(double v) {
 template <int NX, int NU>
 struct Shape {
   static constexpr int NUX = NX + NU;
-  static constexpr int64_t FS = (int64_t)NU * (NU + 1) / 2 + NU + NX * NU + NX * (NX + 1) / 2 + NX;
+  static constexpr int FS = NU * (NU + 1) / 2 + NU + NX * NU + NX * (NX + 1) / 2 + NX;
   static constexpr int ODR = NU * (NU + 1) / 2, OLS = ODR + NU, OLQ = OLS + NX * NU,
                        ODQ = OLQ + NX * (NX + 1) / 2;
+  static constexpr int LC = NX * NUX;   // LDS elements of C per instance
+  static constexpr int LH = NUX * NUX;  // LDS elements of H per instance
 };
 
-// Lane identity shared by the kernels.
+// Lane identity.
 struct Lane {
-  int i, ic, mi;   // row in the instance, clamped input row, clamped state row
+  int lane, g, i, ia, ic, mi;  // lane in wave, instance slot, row, clamped row/input/state index
   bool isu, inst, valid;
-  int b;
-  int64_t bb;      // clamped instance index (a valid one, for loads)
+  int b0, b;
+  int64_t bb;                  // clamped instance index (always a valid instance, for loads)
 };
 
 template <int NX, int NU>
 __device__ __forceinline__ Lane lane_id(int batch) {
   constexpr int NUX = NX + NU;
   Lane L;
-  const int l = threadIdx.x & 63;
-  L.i = l & 15;
-  L.b = blockIdx.x * 4 + (l >> 4);
+  L.lane = threadIdx.x & 63;
+  L.g = L.lane >> 4;
+  L.i = L.lane & 15;
+  L.ia = L.i < NUX ? L.i : NUX - 1;
+  L.b0 = blockIdx.x * 4;
+  L.b = L.b0 + L.g;
   L.inst = L.b < batch;
   L.valid = L.inst && L.i < NUX;
   L.bb = L.inst ? L.b : 0;
@@ -140,64 +156,163 @@ __device__ __forceinline__ Lane lane_id(int batch) {
   return L;
 }
 
-// ------------------------------------------------------------------------------------------
-// Factor sweep
-
-template <int NX, int NU>
-struct FStage {
-  double c[NX];          // column i of [B_k A_k]
-  double h[NX + NU];     // lower part of row i of [[R,S],[S^T,Q]] (symmetrised)
-  double rq;             // r_k[i] (input lanes) or q_k[m] (state lanes)
-  double fk[NX];         // f_k (all lanes)
+template <int BYTES>
+struct VecT;
+template <>
+struct VecT<16> {
+  using type = u4;
+};
+template <>
+struct VecT<8> {
+  using type = u2;
+};
+template <>
+struct VecT<4> {
+  using type = unsigned int;
 };
 
-template <int NX, int NU, bool HS, bool HF>
-__device__ __forceinline__ void load_fstage(FStage<NX, NU>& st, const Lane& L, int k, const lq_data& d,
-                                            int N) {
-  constexpr int NUX = NX + NU;
-  const int64_t bb = L.bb;
-  const double* Ak = d.A + (bb * N + k) * NX * NX;
-  const double* Bk = d.B + (bb * N + k) * NX * NU;
-  const double* Rk = d.R + (bb * N + k) * NU * NU;
-  const double* Qk = d.Q + (bb * (N + 1) + k) * NX * NX;
-  const double* Sk = HS ? d.S + (bb * N + k) * NU * NX : Rk;
-  const double* cp = L.isu ? Bk + L.ic : Ak + L.mi;
-  const int cs = L.isu ? NU : NX;
-#pragma unroll
-  for (int m = 0; m < NX; ++m) st.c[m] = cp[m * cs];
-#pragma unroll
-  for (int j = 0; j < NU; ++j) {
-    const double a1 = L.isu ? Rk[L.ic * NU + j] : (HS ? Sk[j * NX + L.mi] : 0.0);
-    const double a2 = Rk[j * NU + L.ic];
-    st.h[j] = L.isu ? (j <= L.ic ? 0.5 * (a1 + a2) : 0.0) : a1;
-  }
-#pragma unroll
-  for (int j = 0; j < NX; ++j) {
-    const double a1 = Qk[L.mi * NX + j], a2 = Qk[j * NX + L.mi];
-    st.h[NU + j] = (!L.isu && j <= L.mi) ? 0.5 * (a1 + a2) : 0.0;
-  }
-  const double rv = d.r[(bb * N + k) * NU + L.ic];
-  const double qv = d.q[(bb * (N + 1) + k) * NX + L.mi];
-  st.rq = L.isu ? rv : (k > 0 ? qv : 0.0);
-#pragma unroll
-  for (int m = 0; m < NX; ++m) st.fk[m] = HF ? d.f[(bb * N + k) * NX + m] : 0.0;
-  (void)NUX;
+// Chunk width (elements) for moving blocks whose element counts / offsets are multiples of it.
+template <typename T>
+__host__ __device__ constexpr int chunk_w(int a, int b, int c, int d, int e) {
+  return (a % (16 / (int)sizeof(T)) == 0 && b % (16 / (int)sizeof(T)) == 0 && c % (16 / (int)sizeof(T)) == 0 &&
+          d % (16 / (int)sizeof(T)) == 0 && e % (16 / (int)sizeof(T)) == 0)
+             ? 16 / (int)sizeof(T)
+             : ((a % (8 / (int)sizeof(T)) == 0 && b % (8 / (int)sizeof(T)) == 0 &&
+                 c % (8 / (int)sizeof(T)) == 0 && d % (8 / (int)sizeof(T)) == 0 && e % (8 / (int)sizeof(T)) == 0)
+                    ? 8 / (int)sizeof(T)
+                    : 1);
 }
+
+// One staged segment: per instance and stage a contiguous global block of BLK elements (a
+// row-major matrix with rows of RW elements), placed in LDS at instance stride LSTR, row
+// stride RS and element offset O0.  The wavefront's four blocks move as 16-byte chunks where
+// the shape allows (else 8 or 4 bytes), lane c taking chunks c, c + 64, ...
+template <typename T, int BLK, int RW, int RS, int O0, int LSTR>
+struct Seg {
+  static constexpr int W = chunk_w<T>(BLK, RW, RS, O0, LSTR);
+  static constexpr int CPI = BLK / W;
+  static constexpr int TOT = 4 * CPI;
+  static constexpr int NI = (TOT + 63) / 64;
+  using V = typename VecT<W * (int)sizeof(T)>::type;
+  V r[NI];
+
+  // base: array base (instance i's block of stage k at i * istr + k * BLK)
+  __device__ __forceinline__ void load(const T* base, int64_t istr, const Lane& L, int batch, int k) {
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      int c = L.lane + 64 * t;
+      c = c < TOT ? c : TOT - 1;
+      const int g = c / CPI, w = c % CPI;
+      int inst = L.b0 + g;
+      inst = inst < batch ? inst : batch - 1;
+      r[t] = *(const V*)(base + (int64_t)inst * istr + (int64_t)k * BLK + w * W);
+    }
+  }
+  __device__ __forceinline__ void store(T* lds, const Lane& L) const {
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int c = L.lane + 64 * t;
+      if (TOT % 64 == 0 || c < TOT) {
+        const int g = c / CPI, e = (c % CPI) * W;
+        *(V*)(lds + g * LSTR + (e / RW) * RS + O0 + (e % RW)) = r[t];
+      }
+    }
+  }
+};
+
+// Coalesced store of the four instances' blocks of BLK elements from LDS to global memory
+// (instance i's block at i * istr + off).
+template <typename T, int BLK>
+__device__ __forceinline__ void store_blocks(T* gbase, int64_t istr, int64_t off, const T* lds, const Lane& L,
+                                             int batch) {
+  constexpr int W = chunk_w<T>(BLK, BLK, BLK, 0, BLK);
+  using V = typename VecT<W * (int)sizeof(T)>::type;
+  constexpr int CPI = BLK / W, TOT = 4 * CPI, NI = (TOT + 63) / 64;
+#pragma unroll
+  for (int t = 0; t < NI; ++t) {
+    const int c = L.lane + 64 * t;
+    if (c < TOT) {
+      const int g = c / CPI, w = c % CPI;
+      if (L.b0 + g < batch)
+        *(V*)(gbase + (int64_t)(L.b0 + g) * istr + off + w * W) = *(const V*)(lds + g * BLK + w * W);
+    }
+  }
+}
+
+// The stage data of the four instances of a wavefront, staged through LDS.
+template <int NX, int NU, bool HS, bool HF>
+struct StageData {
+  using SH = Shape<NX, NU>;
+  static constexpr int NUX = NX + NU, LC = SH::LC, LH = SH::LH;
+  Seg<double, NX * NU, NU, NUX, 0, LC> B;               // -> C[:, 0:nu]
+  Seg<double, NX * NX, NX, NUX, NU, LC> A;              // -> C[:, nu:]
+  Seg<double, NU * NU, NU, NUX, 0, LH> R;               // -> H[0:nu, 0:nu]
+  Seg<double, NU * NX, NX, NUX, NU, LH> S;              // -> H[0:nu, nu:]
+  Seg<double, NX * NX, NX, NUX, NU * NUX + NU, LH> Q;   // -> H[nu:, nu:]
+  Seg<double, NU, NU, NU, 0, NUX> r;                    // -> RQ[0:nu]
+  Seg<double, NX, NX, NX, NU, NUX> q;                   // -> RQ[nu:]
+  Seg<double, NX, NX, NX, 0, NX> f;                     // -> Fv
+
+  __device__ __forceinline__ void load(const lq_data& d, int N, const Lane& L, int batch, int k, bool withH) {
+    B.load(d.B, (int64_t)N * NX * NU, L, batch, k);
+    A.load(d.A, (int64_t)N * NX * NX, L, batch, k);
+    if (withH) {
+      R.load(d.R, (int64_t)N * NU * NU, L, batch, k);
+      if (HS) S.load(d.S, (int64_t)N * NU * NX, L, batch, k);
+      Q.load(d.Q, (int64_t)(N + 1) * NX * NX, L, batch, k);
+      r.load(d.r, (int64_t)N * NU, L, batch, k);
+      q.load(d.q, (int64_t)(N + 1) * NX, L, batch, k);
+      if (HF) f.load(d.f, (int64_t)N * NX, L, batch, k);
+    }
+  }
+  __device__ __forceinline__ void store(double* sC, double* sH, double* sRQ, double* sFv, const Lane& L,
+                                        bool withH) const {
+    B.store(sC, L);
+    A.store(sC, L);
+    if (withH) {
+      R.store(sH, L);
+      if (HS) S.store(sH, L);
+      Q.store(sH, L);
+      r.store(sRQ, L);
+      q.store(sRQ, L);
+      if (HF) f.store(sFv, L);
+    }
+  }
+};
+
+template <int NX, int NU>
+__device__ __forceinline__ void zero_S_block(double* sH, const Lane& L) {
+  constexpr int NUX = NX + NU, LH = NUX * NUX;
+  for (int e = L.lane; e < 4 * NU * NX; e += 64) {
+    const int gg = e / (NU * NX), w = e % (NU * NX);
+    sH[gg * LH + (w / NX) * NUX + NU + (w % NX)] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Factor sweep
 
 template <int NX, int NU, typename TF, typename TP, bool HS, bool HF>
 __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d, TF* __restrict__ F,
                                                      double* __restrict__ Vws, int32_t* __restrict__ info) {
   using SH = Shape<NX, NU>;
-  constexpr int NUX = SH::NUX;
-  constexpr int64_t FS = SH::FS;
+  constexpr int NUX = SH::NUX, FS = SH::FS, LC = SH::LC, LH = SH::LH;
   static_assert(NUX <= 16, "tile exceeds a 16-lane row");
-  const Lane L = lane_id<NX, NU>(batch);
-  const int i = L.i, ic = L.ic, mi = L.mi;
-  const bool isu = L.isu, valid = L.valid;
+  __shared__ __attribute__((aligned(16))) double sC[4 * LC];
+  __shared__ __attribute__((aligned(16))) double sH[4 * LH];
+  __shared__ __attribute__((aligned(16))) double sRQ[4 * NUX];
+  __shared__ __attribute__((aligned(16))) double sFv[HF ? 4 * NX : 2];
+  __shared__ __attribute__((aligned(16))) TF sOut[4 * FS];
 
-  TF* Fi = F + L.bb * (N + 1) * FS;
+  const Lane L = lane_id<NX, NU>(batch);
+  const int i = L.i, ia = L.ia, ic = L.ic, mi = L.mi, g = L.g;
+  const bool isu = L.isu, valid = L.valid;
   double* rbar = Vws + L.bb * ((int64_t)N * NU + (int64_t)(N + 1) * NX);
   double* pv = rbar + (int64_t)N * NU;
+  if (!HS) zero_S_block<NX, NU>(sH, L);
+
+  StageData<NX, NU, HS, HF> sd;
+  sd.load(d, N, L, batch, N - 1, true);
 
   double h[NUX];
   double lq[NX];
@@ -224,25 +339,38 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
 #pragma unroll
     for (int j = 0; j < NUX; ++j) h[j] = rnd<TF>(h[j]);
     mydinv = rnd<TF>(mydinv);
-    TF* FN = Fi + (int64_t)N * FS;
-    if (valid && !isu) {
+    TF* po = sOut + g * FS;
+    if (!isu && i < NUX) {
 #pragma unroll
       for (int j = 0; j < NX; ++j)
-        if (j <= mi) FN[SH::OLQ + mi * (mi + 1) / 2 + j] = (TF)h[NU + j];
-      FN[SH::ODQ + mi] = (TF)mydinv;
-      pv[(int64_t)N * NX + mi] = pn;
+        if (j <= mi) po[SH::OLQ + mi * (mi + 1) / 2 + j] = (TF)h[NU + j];
+      po[SH::ODQ + mi] = (TF)mydinv;
+      if (valid) pv[(int64_t)N * NX + mi] = pn;
     }
+    store_blocks<TF, FS>(F, (int64_t)(N + 1) * FS, (int64_t)N * FS, sOut, L, batch);
 #pragma unroll
     for (int j = 0; j < NX; ++j) lq[j] = (j <= mi) ? h[NU + j] : 0.0;
   }
 
-  FStage<NX, NU> cur, nxt;
-  load_fstage<NX, NU, HS, HF>(cur, L, N - 1, d, N);
   for (int k = N - 1; k >= 0; --k) {
-    if (k > 0) load_fstage<NX, NU, HS, HF>(nxt, L, k - 1, d, N);
+    sd.store(sC, sH, sRQ, sFv, L, true);
+    if (k > 0) sd.load(d, N, L, batch, k - 1, true);
+    // operands of stage k from LDS
+    const double* pc = sC + g * LC + ia;          // column ia of C: pc[m * NUX]
+    const double* pr = sH + g * LH + ia * NUX;    // row ia of H
+    const double* pk = sH + g * LH + ia;          // column ia of H: pk[j * NUX]
+    double c[NX];
 #pragma unroll
-    for (int j = 0; j < NUX; ++j) h[j] = cur.h[j];
-    double tq = cur.rq;
+    for (int m = 0; m < NX; ++m) c[m] = pc[m * NUX];
+#pragma unroll
+    for (int j = 0; j < NUX; ++j) {
+      const double col = pk[j * NUX];
+      const double v = (!isu && j < NU) ? col : 0.5 * (pr[j] + col);
+      h[j] = j <= i ? v : 0.0;
+    }
+    const double rqv = sRQ[g * NUX + ia];
+    double tq = (isu || k > 0) ? rqv : 0.0;
+
     // trmm V = C^T L^Q_{k+1}; t1 = L^Q_{k+1}^T f_k
     TP v[NX];
     double t1[NX];
@@ -253,16 +381,17 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
     }
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
+      const double fm = HF ? sFv[g * NX + m] : 0.0;
 #pragma unroll
       for (int j = 0; j <= m; ++j) {
         if (sizeof(TP) == 4) {
           const float Lf = bc((float)lq[j], NU + m);
-          v[j] += (TP)cur.c[m] * (TP)Lf;
-          if (HF) t1[j] = fma((double)Lf, cur.fk[m], t1[j]);
+          v[j] += (TP)c[m] * (TP)Lf;
+          if (HF) t1[j] = fma((double)Lf, fm, t1[j]);
         } else {
           const double Ld = bc(lq[j], NU + m);
-          v[j] += (TP)cur.c[m] * (TP)Ld;
-          if (HF) t1[j] = fma(Ld, cur.fk[m], t1[j]);
+          v[j] += (TP)c[m] * (TP)Ld;
+          if (HF) t1[j] = fma(Ld, fm, t1[j]);
         }
       }
     }
@@ -273,7 +402,7 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
       for (int j = 0; j < NX; ++j) wv = fma(lq[j], t1[j], wv);
     }
 #pragma unroll
-    for (int m = 0; m < NX; ++m) tq = fma(cur.c[m], bc(wv, NU + m), tq);
+    for (int m = 0; m < NX; ++m) tq = fma(c[m], bc(wv, NU + m), tq);
     // syrk Hhat = H + V V^T
 #pragma unroll
     for (int j = 0; j < NUX; ++j) {
@@ -296,31 +425,31 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
       const double rb = bc(tq * mydinv, j);
       tq = (i > j) ? fma(-h[j], rb, tq) : tq;
     }
-    // stores
-    TF* Fk = Fi + (int64_t)k * FS;
-    if (valid) {
+    // factor rows -> LDS block -> coalesced global store
+    TF* po = sOut + g * FS;
+    if (i < NUX) {
       if (isu) {
 #pragma unroll
         for (int j = 0; j < NU; ++j)
-          if (j <= ic) Fk[ic * (ic + 1) / 2 + j] = (TF)h[j];
-        Fk[SH::ODR + ic] = (TF)mydinv;
-        rbar[(int64_t)k * NU + ic] = tq * mydinv;
+          if (j <= ic) po[ic * (ic + 1) / 2 + j] = (TF)h[j];
+        po[SH::ODR + ic] = (TF)mydinv;
       } else {
 #pragma unroll
-        for (int j = 0; j < NU; ++j) Fk[SH::OLS + mi * NU + j] = (TF)h[j];
-        if (k > 0) {
+        for (int j = 0; j < NU; ++j) po[SH::OLS + mi * NU + j] = (TF)h[j];
 #pragma unroll
-          for (int j = 0; j < NX; ++j)
-            if (j <= mi) Fk[SH::OLQ + mi * (mi + 1) / 2 + j] = (TF)h[NU + j];
-          Fk[SH::ODQ + mi] = (TF)mydinv;
-          pv[(int64_t)k * NX + mi] = tq;
-        }
+        for (int j = 0; j < NX; ++j)
+          if (j <= mi) po[SH::OLQ + mi * (mi + 1) / 2 + j] = (TF)h[NU + j];
+        po[SH::ODQ + mi] = (TF)mydinv;
       }
+    }
+    store_blocks<TF, FS>(F, (int64_t)(N + 1) * FS, (int64_t)k * FS, sOut, L, batch);
+    if (valid) {
+      if (isu) rbar[(int64_t)k * NU + ic] = tq * mydinv;
+      else if (k > 0) pv[(int64_t)k * NX + mi] = tq;
     }
     pn = tq;
 #pragma unroll
     for (int j = 0; j < NX; ++j) lq[j] = (j <= mi) ? h[NU + j] : 0.0;
-    if (k > 0) cur = nxt;
   }
   if (L.inst && i == 0) info[L.b] = code;
 }
@@ -330,176 +459,122 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
 
 template <int NX, int NU, typename TF, bool HS, bool HF>
 struct SolveCtx {
-  using SH = Shape<NX, NU>;
   Lane L;
-  int N;
-  const TF* F;             // this instance's factor blocks
+  int N, batch;
+  const TF* F;             // factor region base (all instances)
   lq_data d;
-  const double *rb0, *p0;  // factor-time sweep vectors
+  const double *rb0, *p0;  // this instance's factor-time sweep vectors
   double *rb2, *p2, *flam, *rhou, *rhox;
   double *x, *u, *lam;
-  __device__ double LRv(int k, int row, int col) const { return (double)F[k * SH::FS + row * (row + 1) / 2 + col]; }
-  __device__ double LSv(int k, int row, int col) const { return (double)F[k * SH::FS + SH::OLS + row * NU + col]; }
-  __device__ double LQv(int k, int row, int col) const {
-    return (double)F[k * SH::FS + SH::OLQ + row * (row + 1) / 2 + col];
-  }
-  __device__ double dRv(int k, int row) const { return (double)F[k * SH::FS + SH::ODR + row]; }
+  TF* sF;                  // LDS: two stage slots x 4 instances x FS
+  double *sC, *sH, *sRQ, *sFv;
 };
 
-// Forward-pass operands of stage k, loaded ahead of time.
-template <int NX, int NU>
-struct FwdStage {
-  double g[NX];    // input lanes: column ic of L^S_k;  state lanes: row mi of A_k
-  double e[NU];    // input lanes: L^R_k[j][ic] (j > ic used);  state lanes: row mi of B_k
-  double s0;       // input lanes: rbar_k[ic];  state lanes: f_k[mi] (or flam_k[mi])
-  double s1;       // input lanes: 1 / L^R_k[ic][ic];  state lanes: p_{k+1}[mi]
+// Per-lane operands of forward stage k (contiguous per instance), loaded a stage ahead.
+struct FwdVec {
+  double s0;          // input lanes: rbar_k[ic];  state lanes: f_k[mi] (mode 0) or flam_k[mi]
+  double s1;          // state lanes: p_{k+1}[mi]
   double zu, zx, zl;  // old iterate (correction passes): u_k[ic], x_{k+1}[mi], lam_k[mi]
 };
 
-// State lanes: column / row mi of L^Q_{k+1} (rows >= mi, cols <= mi used); loaded at the top
-// of stage k, consumed after the rollout step.
-template <int NX>
-struct LqRowCol {
-  double lc[NX], lr[NX];
-};
-
 template <int NX, int NU, typename TF, bool HS, bool HF>
-__device__ __forceinline__ void load_fwd(FwdStage<NX, NU>& st, const SolveCtx<NX, NU, TF, HS, HF>& s, int k,
-                                         int mode) {
+__device__ __forceinline__ void load_fwdvec(FwdVec& v, const SolveCtx<NX, NU, TF, HS, HF>& s, int k, int mode) {
   const Lane& L = s.L;
-  const int N = s.N;
-  const int64_t bb = L.bb;
-  const double* Ak = s.d.A + (bb * N + k) * NX * NX;
-  const double* Bk = s.d.B + (bb * N + k) * NX * NU;
-  using SH = Shape<NX, NU>;
-  // input lanes: column ic of L^S_k (stride nu) and L^R_k[j][ic] at j(j+1)/2 + ic (inside the
-  // packed L^R block for every j < nu); state lanes: rows mi of A_k and B_k
-  const TF* fb = s.F + (int64_t)k * SH::FS;
-  const TF* gsp = fb + SH::OLS + L.ic;
-  const TF* erp = fb + L.ic;
-  const double* ap = Ak + L.mi * NX;
-  const double* bp = Bk + L.mi * NU;
-#pragma unroll
-  for (int m = 0; m < NX; ++m) {
-    const double gs = (double)gsp[m * NU];
-    st.g[m] = L.isu ? gs : ap[m];
-  }
-#pragma unroll
-  for (int j = 0; j < NU; ++j) {
-    const double er = (double)erp[j * (j + 1) / 2];
-    st.e[j] = L.isu ? er : bp[j];
-  }
   const double* rbv = mode == 0 ? s.rb0 : s.rb2;
   const double* pvv = mode == 0 ? s.p0 : s.p2;
   double fv;
-  if (mode == 0) fv = HF ? s.d.f[(bb * N + k) * NX + L.mi] : 0.0;
+  if (mode == 0) fv = HF ? s.d.f[(L.bb * s.N + k) * NX + L.mi] : 0.0;
   else fv = s.flam[(int64_t)k * NX + L.mi];
-  st.s0 = L.isu ? rbv[(int64_t)k * NU + L.ic] : fv;
-  st.s1 = L.isu ? s.dRv(k, L.ic) : pvv[(int64_t)(k + 1) * NX + L.mi];
+  const double rv = rbv[(int64_t)k * NU + L.ic];
+  v.s0 = L.isu ? rv : fv;
+  v.s1 = pvv[(int64_t)(k + 1) * NX + L.mi];
   if (mode == 1) {
-    st.zu = s.u[(int64_t)k * NU + L.ic];
-    st.zx = s.x[(int64_t)k * NX + L.mi];
-    st.zl = s.lam[(int64_t)k * NX + L.mi];
+    v.zu = s.u[(int64_t)k * NU + L.ic];
+    v.zx = s.x[(int64_t)k * NX + L.mi];
+    v.zl = s.lam[(int64_t)k * NX + L.mi];
   } else {
-    st.zu = st.zx = st.zl = 0.0;
+    v.zu = v.zx = v.zl = 0.0;
   }
 }
 
-// Column mi of the packed lower L^Q at rows m >= mi sits at m(m+1)/2 + mi, row mi at
-// mi(mi+1)/2 + j: one per-lane base plus compile-time offsets.  Masked entries read other
-// elements of the same packed block (all offsets stay below nx(nx+1)/2).
-template <int NX, int NU, typename TF, bool HS, bool HF>
-__device__ __forceinline__ void load_lq(LqRowCol<NX>& st, const SolveCtx<NX, NU, TF, HS, HF>& s, int k) {
-  using SH = Shape<NX, NU>;
-  const int mi = s.L.mi;
-  const TF* blk = s.F + (int64_t)k * SH::FS + SH::OLQ;
-  const TF* pc = blk + mi;
-  const TF* pr = blk + mi * (mi + 1) / 2;
-#pragma unroll
-  for (int m = 0; m < NX; ++m) {
-    st.lc[m] = (double)pc[m * (m + 1) / 2];
-    st.lr[m] = (double)pr[m];
-  }
-}
-
-// Residual operands of stage k.
-template <int NX, int NU>
-struct ResStage {
-  double g1[NX];   // input lanes: row ic of S_k;  state lanes: row mi of sym(Q_k)
-  double g2[NX];   // input lanes: column ic of B_k;  state lanes: column mi of A_k
-  double e[NU];    // input lanes: row ic of sym(R_k);  state lanes: column mi of S_k
-  double rq;       // r_k[ic] or q_k[mi]
-  double fo;       // f_k[mi] (original right-hand side)
-};
-
-template <int NX, int NU, typename TF, bool HS, bool HF>
-__device__ __forceinline__ void load_res(ResStage<NX, NU>& st, const SolveCtx<NX, NU, TF, HS, HF>& s, int k) {
-  const Lane& L = s.L;
-  const int N = s.N;
-  const int64_t bb = L.bb;
-  const double* Ak = s.d.A + (bb * N + k) * NX * NX;
-  const double* Bk = s.d.B + (bb * N + k) * NX * NU;
-  const double* Rk = s.d.R + (bb * N + k) * NU * NU;
-  const double* Qk = s.d.Q + (bb * (N + 1) + k) * NX * NX;
-  const double* Sk = HS ? s.d.S + (bb * N + k) * NU * NX : Rk;
-#pragma unroll
-  for (int m = 0; m < NX; ++m) {
-    const double q1 = Qk[L.mi * NX + m], q2 = Qk[m * NX + L.mi];
-    const double sr = HS ? Sk[L.ic * NX + m] : 0.0;
-    st.g1[m] = L.isu ? sr : 0.5 * (q1 + q2);
-    st.g2[m] = L.isu ? Bk[m * NU + L.ic] : Ak[m * NX + L.mi];
-  }
-#pragma unroll
-  for (int j = 0; j < NU; ++j) {
-    const double r1 = Rk[L.ic * NU + j], r2 = Rk[j * NU + L.ic];
-    const double sc = HS ? Sk[j * NX + L.mi] : 0.0;
-    st.e[j] = L.isu ? 0.5 * (r1 + r2) : sc;
-  }
-  const double rv = s.d.r[(bb * N + k) * NU + L.ic];
-  const double qv = s.d.q[(bb * (N + 1) + k) * NX + L.mi];
-  st.rq = L.isu ? rv : qv;
-  st.fo = HF ? s.d.f[(bb * N + k) * NX + L.mi] : 0.0;
-}
+// Factor block of one stage for the four instances.
+template <int NX, int NU, typename TF>
+using FSeg = Seg<TF, Shape<NX, NU>::FS, Shape<NX, NU>::FS, Shape<NX, NU>::FS, 0, Shape<NX, NU>::FS>;
 
 // One forward pass.  mode 0: z = solution (x_0 = x_init, f = f_k, sweep vectors of lq_factor);
 // mode 1: z += correction (dx_0 = 0, f = flam, sweep vectors rbar2/p2).  With `res`, computes
 // the KKT residual of the updated iterate on the fly (and stores it when `store`); returns
-// rel_res (uniform over the instance's 16 lanes), or 0 without `res`.
+// rel_res (uniform over the instance's 16 lanes), or 0 without `res`.  Lanes of instances with
+// act == false store nothing.
 template <int NX, int NU, typename TF, bool HS, bool HF>
-__device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool res, bool store) {
-  constexpr int NUX = NX + NU;
+__device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool res, bool store, bool act) {
+  using SH = Shape<NX, NU>;
+  constexpr int NUX = SH::NUX, FS = SH::FS, LC = SH::LC, LH = SH::LH;
   const Lane& L = s.L;
-  const int N = s.N, i = L.i, mi = L.mi, ic = L.ic;
-  const bool isu = L.isu, xl = L.valid && !L.isu, ul = L.valid && L.isu;
+  const int N = s.N, batch = s.batch, i = L.i, ia = L.ia, mi = L.mi, ic = L.ic, g = L.g;
+  const bool isu = L.isu, xl = act && L.valid && !L.isu, ul = act && L.valid && L.isu;
+  const int64_t fistr = (int64_t)(N + 1) * FS;
   const double x0v = s.d.x0[L.bb * NX + mi];
   double xc = (mode == 0 && !isu) ? x0v : 0.0;  // recursion state (x_k or dx_k)
   double xk = isu ? 0.0 : x0v;                   // updated iterate x_k (x_0 = x_init)
   double lkm = 0.0;                              // updated lam_{k-1}
   double mr = 0.0, mb = 0.0;
-  FwdStage<NX, NU> cur, nxt;
-  load_fwd<NX, NU, TF, HS, HF>(cur, s, 0, mode);
+
+  // prologue: factor slots 0, 1 and stage-0 data in LDS; stage-1 data and F_2 in flight
+  {
+    FSeg<NX, NU, TF> f0, f1;
+    f0.load(s.F, fistr, L, batch, 0);
+    f1.load(s.F, fistr, L, batch, 1);
+    StageData<NX, NU, HS, HF> d0;
+    d0.load(s.d, N, L, batch, 0, res);
+    f0.store(s.sF, L);
+    f1.store(s.sF + 4 * FS, L);
+    d0.store(s.sC, s.sH, s.sRQ, s.sFv, L, res);
+  }
+  FSeg<NX, NU, TF> fn;
+  StageData<NX, NU, HS, HF> dn;
+  if (N > 1) {
+    dn.load(s.d, N, L, batch, 1, res);
+    fn.load(s.F, fistr, L, batch, 2);
+  }
+  FwdVec cur, nxt;
+  load_fwdvec<NX, NU, TF, HS, HF>(cur, s, 0, mode);
+
   for (int k = 0; k < N; ++k) {
-    if (k + 1 < N) load_fwd<NX, NU, TF, HS, HF>(nxt, s, k + 1, mode);
-    LqRowCol<NX> lq;
-    load_lq<NX, NU, TF, HS, HF>(lq, s, k + 1);
-    ResStage<NX, NU> rs;
-    if (res) load_res<NX, NU, TF, HS, HF>(rs, s, k);
+    if (k > 0) {
+      // stage k data and F_{k+1} into LDS (slot (k+1) & 1 held F_{k-1}, no longer needed)
+      dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, res);
+      fn.store(s.sF + ((k + 1) & 1) * 4 * FS, L);
+      if (k + 1 < N) {
+        dn.load(s.d, N, L, batch, k + 1, res);
+        fn.load(s.F, fistr, L, batch, k + 2);
+      }
+    }
+    if (k + 1 < N) load_fwdvec<NX, NU, TF, HS, HF>(nxt, s, k + 1, mode);
+    const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;          // F_k of this instance
+    const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;   // F_{k+1}
+    const double* prC = s.sC + g * LC + ia;                    // column ia of C (stride NUX)
+    const double* prA = s.sC + g * LC + mi * NUX;              // row mi of C = [B row, A row]
+
     // t = rbar + L^S^T x on input lanes
     double t = cur.s0, t_b = 0.0;
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       const double xb = bc(xc, NU + m);
-      if (m & 1) t_b = fma(cur.g[m], xb, t_b);
-      else t = fma(cur.g[m], xb, t);
+      const double gv = (double)Fk[SH::OLS + m * NU + ic];
+      if (m & 1) t_b = fma(gv, xb, t_b);
+      else t = fma(gv, xb, t);
     }
     t += t_b;
     // u' = L^R^{-T} t, u = -u'
+    const double dRi = (double)Fk[SH::ODR + ic];
     double uu = 0.0;
 #pragma unroll
     for (int j = NU - 1; j >= 0; --j) {
-      const double uj = bc(t * cur.s1, j);
+      const double uj = bc(t * dRi, j);
       uu = (i == j) ? uj : uu;
-      t = (i < j) ? fma(-cur.e[j], uj, t) : t;
+      const double e = (double)Fk[j * (j + 1) / 2 + ic];  // L^R[j][ic] for ic < j (in-block otherwise)
+      t = (i < j) ? fma(-e, uj, t) : t;
     }
     const double du = -uu;
     // x_{k+1} = A x + B u + f on state lanes
@@ -507,24 +582,26 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
 #pragma unroll
     for (int n = 0; n < NX; ++n) {
       const double xb = bc(xc, NU + n);
-      if (n & 1) xn_b = fma(cur.g[n], xb, xn_b);
-      else xn = fma(cur.g[n], xb, xn);
+      if (n & 1) xn_b = fma(prA[NU + n], xb, xn_b);
+      else xn = fma(prA[NU + n], xb, xn);
     }
 #pragma unroll
-    for (int j = 0; j < NU; ++j) xn = fma(cur.e[j], bc(du, j), xn);
+    for (int j = 0; j < NU; ++j) xn = fma(prA[j], bc(du, j), xn);
     xn += xn_b;
     // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}
+    const TF* lqc = Fk1 + SH::OLQ + mi;                    // column mi: + m(m+1)/2
+    const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;     // row mi: + j
     double t2 = 0.0;
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       const double xb = bc(xn, NU + m);
-      t2 = (m >= mi) ? fma(lq.lc[m], xb, t2) : t2;
+      t2 = (m >= mi) ? fma((double)lqc[m * (m + 1) / 2], xb, t2) : t2;
     }
     double lm = cur.s1;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       const double tb = bc(t2, NU + j);
-      lm = (j <= mi) ? fma(lq.lr[j], tb, lm) : lm;
+      lm = (j <= mi) ? fma((double)lqr[j], tb, lm) : lm;
     }
     // updated iterate
     const double unew = du + cur.zu;
@@ -536,19 +613,21 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       s.lam[(int64_t)k * NX + mi] = lnew;
     }
     if (res) {
+      const double* hr = s.sH + g * LH + ia * NUX;   // row ia of H
+      const double* hc = s.sH + g * LH + ia;         // column ia of H (stride NUX)
       // residual rows of stage k at the updated iterate (x_k = xk, u_k, lam_k, x_{k+1}, lam_{k-1})
-      double au = 0.0, au2 = 0.0, bu = 0.0;  // R u + S x_k + B^T lam ;  S_0 x_init
-      double al = -xnew, bl = 0.0;           // A x_k + B u - x_{k+1} ;  A_0 x_init
-      double ax = -lkm, ax2 = 0.0;           // S^T u + Q x_k + A^T lam - lam_{k-1}
+      double au = 0.0, ab = 0.0, bu = 0.0;  // S x_k + R u (input) ; B^T lam (input) / A^T lam (state)
+      double al = -xnew, bl = 0.0;          // A x_k + B u - x_{k+1} ;  A_0 x_init
+      double ax = -lkm;                     // Q x_k + S^T u - lam_{k-1} (+ A^T lam)
 #pragma unroll
       for (int n = 0; n < NX; ++n) {
         const double xb = bc(xk, NU + n);
         const double lb = bc(lnew, NU + n);
-        if (HS) au = fma(rs.g1[n], xb, au);      // input lanes: S row
-        au2 = fma(rs.g2[n], lb, au2);            // input lanes: B column -> B^T lam
-        al = fma(cur.g[n], xb, al);              // state lanes: A row
-        ax = fma(rs.g1[n], xb, ax);              // state lanes: sym Q row
-        ax2 = fma(rs.g2[n], lb, ax2);            // state lanes: A column -> A^T lam
+        const double hrow = hr[NU + n], hcol = hc[(NU + n) * NUX];
+        if (HS) au = fma(hrow, xb, au);           // input lanes: S row
+        ab = fma(prC[n * NUX], lb, ab);           // column ia of C: B^T lam (input), A^T lam (state)
+        al = fma(prA[NU + n], xb, al);            // state lanes: A row
+        ax = fma(0.5 * (hrow + hcol), xb, ax);    // state lanes: sym Q row
       }
       if (k == 0) {
         bu = HS ? au : 0.0;
@@ -557,25 +636,28 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
 #pragma unroll
       for (int j = 0; j < NU; ++j) {
         const double ub = bc(unew, j);
-        au = fma(rs.e[j], ub, au);               // input lanes: sym R row
-        al = fma(cur.e[j], ub, al);              // state lanes: B row
-        if (HS) ax = fma(rs.e[j], ub, ax);       // state lanes: S column -> S^T u
+        const double hrow = hr[j], hcol = hc[j * NUX];
+        au = fma(0.5 * (hrow + hcol), ub, au);    // input lanes: sym R row
+        al = fma(prA[j], ub, al);                 // state lanes: B row
+        if (HS) ax = fma(hcol, ub, ax);           // state lanes: S column -> S^T u
       }
-      au += au2;
-      ax += ax2;
-      const double rhou = -rs.rq - au;
-      const double rhol = -rs.fo - al;
-      const double rhox = -rs.rq - ax;
+      au += ab;
+      ax += ab;
+      const double rq = s.sRQ[g * NUX + ia];
+      const double fo = HF ? s.sFv[g * NX + mi] : 0.0;
+      const double rhou = -rq - au;
+      const double rhol = -fo - al;
+      const double rhox = -rq - ax;
       if (ul) {
         mr = fmax(mr, fabs(rhou));
-        mb = fmax(mb, fabs(rs.rq + bu));
+        mb = fmax(mb, fabs(rq + bu));
       }
       if (xl) {
         mr = fmax(mr, fabs(rhol));
-        mb = fmax(mb, fabs(rs.fo + bl));
+        mb = fmax(mb, fabs(fo + bl));
         if (k > 0) {
           mr = fmax(mr, fabs(rhox));
-          mb = fmax(mb, fabs(rs.rq));
+          mb = fmax(mb, fabs(rq));
         }
       }
       if (store) {
@@ -612,109 +694,119 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     mb = rowmax(mb);
     return mb > 0.0 ? mr / mb : mr;
   }
-  (void)NUX;
   return 0.0;
 }
 
 // Backward sweep of the correction right-hand side (r, q, f) = (-rho_u, -rho_x, -rho_l),
-// x_init = 0, into (rbar2, p2).
-template <int NX, int NU>
-struct BwdStage {
-  double lc[NX], lr[NX];  // state lanes: column / row mi of L^Q_{k+1}
-  double cc[NX];          // column i of [B_k A_k]
-  double hr[NU];          // input lanes: row ic of L^R_k;  state lanes: row mi of L^S_k
-  double dr;              // 1 / L^R_k[ic][ic]
-  double rho;             // rho_u,k[ic] or rho_x,k[mi]
-  double fl;              // flam_k[mi] = -rho_l,k
-};
-
+// x_init = 0, into (rbar2, p2).  Lanes of instances with act == false store nothing.
 template <int NX, int NU, typename TF, bool HS, bool HF>
-__device__ __forceinline__ void load_bwd(BwdStage<NX, NU>& st, const SolveCtx<NX, NU, TF, HS, HF>& s, int k) {
-  const Lane& L = s.L;
-  const int N = s.N;
-  const int64_t bb = L.bb;
-  const double* Ak = s.d.A + (bb * N + k) * NX * NX;
-  const double* Bk = s.d.B + (bb * N + k) * NX * NU;
+__device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
   using SH = Shape<NX, NU>;
-  const TF* blk = s.F + (int64_t)(k + 1) * SH::FS + SH::OLQ;
-  const TF* pc = blk + L.mi;
-  const TF* pr = blk + L.mi * (L.mi + 1) / 2;
-  const double* cp = L.isu ? Bk + L.ic : Ak + L.mi;
-  const int cs = L.isu ? NU : NX;
-#pragma unroll
-  for (int m = 0; m < NX; ++m) {
-    st.lc[m] = (double)pc[m * (m + 1) / 2];
-    st.lr[m] = (double)pr[m];
-    st.cc[m] = cp[m * cs];
-  }
-  // input lanes: row ic of packed L^R (entries j <= ic; j > ic reads stay inside the block);
-  // state lanes: row mi of L^S
-  const TF* hp = L.isu ? s.F + (int64_t)k * SH::FS + L.ic * (L.ic + 1) / 2
-                       : s.F + (int64_t)k * SH::FS + SH::OLS + L.mi * NU;
-#pragma unroll
-  for (int j = 0; j < NU; ++j) {
-    const double v = (double)hp[j];
-    st.hr[j] = (L.isu && j > L.ic) ? 0.0 : v;
-  }
-  st.dr = s.dRv(k, L.ic);
-  st.rho = L.isu ? s.rhou[(int64_t)k * NU + L.ic] : s.rhox[(int64_t)k * NX + L.mi];
-  st.fl = s.flam[(int64_t)k * NX + L.mi];
-}
-
-template <int NX, int NU, typename TF, bool HS, bool HF>
-__device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s) {
+  constexpr int NUX = SH::NUX, FS = SH::FS, LC = SH::LC;
   const Lane& L = s.L;
-  const int N = s.N, i = L.i, mi = L.mi, ic = L.ic;
-  const bool isu = L.isu, xl = L.valid && !L.isu, ul = L.valid && L.isu;
+  const int N = s.N, batch = s.batch, i = L.i, ia = L.ia, mi = L.mi, ic = L.ic, g = L.g;
+  const bool isu = L.isu, xl = act && L.valid && !L.isu, ul = act && L.valid && L.isu;
+  const int64_t fistr = (int64_t)(N + 1) * FS;
   double p2n = -s.rhox[(int64_t)N * NX + mi];
   if (xl) s.p2[(int64_t)N * NX + mi] = p2n;
-  BwdStage<NX, NU> cur, nxt;
-  load_bwd<NX, NU, TF, HS, HF>(cur, s, N - 1);
+  {
+    FSeg<NX, NU, TF> fa, fb;
+    fa.load(s.F, fistr, L, batch, N);
+    fb.load(s.F, fistr, L, batch, N - 1);
+    StageData<NX, NU, HS, HF> d0;
+    d0.load(s.d, N, L, batch, N - 1, false);
+    fa.store(s.sF + (N & 1) * 4 * FS, L);
+    fb.store(s.sF + ((N - 1) & 1) * 4 * FS, L);
+    d0.store(s.sC, s.sH, s.sRQ, s.sFv, L, false);
+  }
+  FSeg<NX, NU, TF> fn;
+  StageData<NX, NU, HS, HF> dn;
+  if (N > 1) {
+    fn.load(s.F, fistr, L, batch, N - 2);
+    dn.load(s.d, N, L, batch, N - 2, false);
+  }
+  double rho = isu ? s.rhou[(int64_t)(N - 1) * NU + ic] : s.rhox[(int64_t)(N - 1) * NX + mi];
+  double fl = s.flam[(int64_t)(N - 1) * NX + mi];
   for (int k = N - 1; k >= 0; --k) {
-    if (k > 0) load_bwd<NX, NU, TF, HS, HF>(nxt, s, k - 1);
+    if (k < N - 1) {
+      // F_k into slot k & 1 (held F_{k+2}, no longer needed), stage-k data into LDS
+      fn.store(s.sF + (k & 1) * 4 * FS, L);
+      dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, false);
+      if (k > 0) {
+        fn.load(s.F, fistr, L, batch, k - 1);
+        dn.load(s.d, N, L, batch, k - 1, false);
+      }
+    }
+    double rho_n = 0.0, fl_n = 0.0;
+    if (k > 0) {
+      const double ru = s.rhou[(int64_t)(k - 1) * NU + ic], rx = s.rhox[(int64_t)(k - 1) * NX + mi];
+      rho_n = isu ? ru : rx;
+      fl_n = s.flam[(int64_t)(k - 1) * NX + mi];
+    }
+    const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;
+    const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;
     // t1 = L^Q_{k+1}^T f', w = L^Q_{k+1} t1 + p2_{k+1}
+    const TF* lqc = Fk1 + SH::OLQ + mi;
+    const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;
     double t1 = 0.0;
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double fb = bc(cur.fl, NU + m);
-      t1 = (m >= mi) ? fma(cur.lc[m], fb, t1) : t1;
+      const double fb = bc(fl, NU + m);
+      t1 = (m >= mi) ? fma((double)lqc[m * (m + 1) / 2], fb, t1) : t1;
     }
     double w = p2n;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       const double tb = bc(t1, NU + j);
-      w = (j <= mi) ? fma(cur.lr[j], tb, w) : w;
+      w = (j <= mi) ? fma((double)lqr[j], tb, w) : w;
     }
-    double tq = (isu || k > 0) ? -cur.rho : 0.0, tq_b = 0.0;
+    const double* prC = s.sC + g * LC + ia;
+    double tq = (isu || k > 0) ? -rho : 0.0, tq_b = 0.0;
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       const double wb = bc(w, NU + m);
-      if (m & 1) tq_b = fma(cur.cc[m], wb, tq_b);
-      else tq = fma(cur.cc[m], wb, tq);
+      if (m & 1) tq_b = fma(prC[m * NUX], wb, tq_b);
+      else tq = fma(prC[m * NUX], wb, tq);
     }
     tq += tq_b;
+    // input lanes: row ic of L^R (packed); state lanes: row mi of L^S
+    const TF* hp = isu ? Fk + ic * (ic + 1) / 2 : Fk + SH::OLS + mi * NU;
+    const double dr = (double)Fk[SH::ODR + ic];
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
-      const double rb = bc(tq * cur.dr, j);
-      tq = (i > j) ? fma(-cur.hr[j], rb, tq) : tq;
+      const double rb = bc(tq * dr, j);
+      const double hv = (double)hp[j];
+      tq = (i > j) ? fma(-hv, rb, tq) : tq;
     }
-    if (ul) s.rb2[(int64_t)k * NU + ic] = tq * cur.dr;
+    if (ul) s.rb2[(int64_t)k * NU + ic] = tq * dr;
     if (xl && k > 0) s.p2[(int64_t)k * NX + mi] = tq;
     p2n = tq;
-    if (k > 0) cur = nxt;
+    rho = rho_n;
+    fl = fl_n;
   }
 }
 
 template <int NX, int NU, typename TF, bool HS, bool HF>
 __global__ void __launch_bounds__(64) k_solve_small(SolveArgs a, int N) {
-  using Ctx = SolveCtx<NX, NU, TF, HS, HF>;
-  constexpr int64_t FS = Shape<NX, NU>::FS;
-  Ctx s;
+  using SH = Shape<NX, NU>;
+  constexpr int NUX = SH::NUX, FS = SH::FS, LC = SH::LC, LH = SH::LH;
+  __shared__ __attribute__((aligned(16))) TF sF[2 * 4 * FS];
+  __shared__ __attribute__((aligned(16))) double sC[4 * LC];
+  __shared__ __attribute__((aligned(16))) double sH[4 * LH];
+  __shared__ __attribute__((aligned(16))) double sRQ[4 * NUX];
+  __shared__ __attribute__((aligned(16))) double sFv[HF ? 4 * NX : 2];
+  SolveCtx<NX, NU, TF, HS, HF> s;
   s.L = lane_id<NX, NU>(a.batch);
   s.N = N;
+  s.batch = a.batch;
   s.d = a.d;
+  s.F = (const TF*)a.F;
+  s.sF = sF;
+  s.sC = sC;
+  s.sH = sH;
+  s.sRQ = sRQ;
+  s.sFv = sFv;
   const int64_t bb = s.L.bb;
-  s.F = (const TF*)a.F + bb * (N + 1) * FS;
   const int64_t vst = (int64_t)N * NU + (int64_t)(N + 1) * NX;
   s.rb0 = a.V + bb * vst;
   s.p0 = s.rb0 + (int64_t)N * NU;
@@ -727,20 +819,18 @@ __global__ void __launch_bounds__(64) k_solve_small(SolveArgs a, int N) {
   s.x = a.x + bb * N * NX;
   s.u = a.u + bb * N * NU;
   s.lam = a.lam + bb * N * NX;
+  if (!HS) zero_S_block<NX, NU>(sH, s.L);
 
   const bool res = a.check || a.max_it > 0;
   int it = 0;
-  double rel = 0.0;
-  bool act = false;
-  if (s.L.inst) {
-    rel = fwd_res<NX, NU, TF, HS, HF>(s, 0, res, a.max_it > 0);
-    act = a.max_it > 0 && rel > a.tol;
-  }
+  double rel = fwd_res<NX, NU, TF, HS, HF>(s, 0, res, a.max_it > 0, s.L.inst);
+  bool act = s.L.inst && a.max_it > 0 && rel > a.tol;
   while (__any(act)) {
+    bwd_corr<NX, NU, TF, HS, HF>(s, act);
+    const double r2 = fwd_res<NX, NU, TF, HS, HF>(s, 1, true, it + 1 < a.max_it, act);
     if (act) {
-      bwd_corr<NX, NU, TF, HS, HF>(s);
       ++it;
-      rel = fwd_res<NX, NU, TF, HS, HF>(s, 1, true, it < a.max_it);
+      rel = r2;
       act = it < a.max_it && rel > a.tol;
     }
   }
@@ -759,6 +849,9 @@ __global__ void __launch_bounds__(64) k_solve_small(SolveArgs a, int N) {
       }
     }
   }
+  (void)LC;
+  (void)LH;
+  (void)NUX;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -801,6 +894,15 @@ bool small_variant_available(lq_mode mode, int nx, int nu) {
   LQ_SMALL_SHAPES(X)
 #undef X
   return false;
+}
+
+// The staged loads move 16-byte chunks: every array of the problem, the workspace and the
+// outputs must be 16-byte aligned.
+bool small_aligned(const lq_data& d, const void* ws) {
+  const void* p[] = {d.A, d.B, d.Q, d.R, d.S, d.q, d.r, d.f, d.x0, ws};
+  for (const void* q : p)
+    if (q && ((uintptr_t)q & 15)) return false;
+  return true;
 }
 
 hipError_t launch_factor_small(lq_mode mode, int batch, int N, int nx, int nu, const lq_data& d, void* F,

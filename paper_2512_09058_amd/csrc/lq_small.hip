@@ -125,8 +125,12 @@ struct Shape {
   static constexpr int FS = NU * (NU + 1) / 2 + NU + NX * NU + NX * (NX + 1) / 2 + NX;
   static constexpr int ODR = NU * (NU + 1) / 2, OLS = ODR + NU, OLQ = OLS + NX * NU,
                        ODQ = OLQ + NX * (NX + 1) / 2;
-  static constexpr int LC = NX * NUX;   // LDS elements of C per instance
-  static constexpr int LH = NUX * NUX;  // LDS elements of H per instance
+  // LDS tiles: rows padded to RSP = nx + nu + 2 elements and instance tiles to a stride that
+  // is 8 doubles past a multiple of 32, so that row-wise reads of different lanes and the
+  // four instances of a wavefront fall into different LDS banks.
+  static constexpr int RSP = NUX + 2;
+  static constexpr int LC = (NX * RSP + 31) / 32 * 32 + 8;   // LDS elements of C per instance
+  static constexpr int LH = (NUX * RSP + 31) / 32 * 32 + 8;  // LDS elements of H per instance
 };
 
 // Lane identity.
@@ -243,12 +247,12 @@ __device__ __forceinline__ void store_blocks(T* gbase, int64_t istr, int64_t off
 template <int NX, int NU, bool HS, bool HF>
 struct StageData {
   using SH = Shape<NX, NU>;
-  static constexpr int NUX = NX + NU, LC = SH::LC, LH = SH::LH;
-  Seg<double, NX * NU, NU, NUX, 0, LC> B;               // -> C[:, 0:nu]
-  Seg<double, NX * NX, NX, NUX, NU, LC> A;              // -> C[:, nu:]
-  Seg<double, NU * NU, NU, NUX, 0, LH> R;               // -> H[0:nu, 0:nu]
-  Seg<double, NU * NX, NX, NUX, NU, LH> S;              // -> H[0:nu, nu:]
-  Seg<double, NX * NX, NX, NUX, NU * NUX + NU, LH> Q;   // -> H[nu:, nu:]
+  static constexpr int NUX = NX + NU, LC = SH::LC, LH = SH::LH, RSP = SH::RSP;
+  Seg<double, NX * NU, NU, RSP, 0, LC> B;               // -> C[:, 0:nu]
+  Seg<double, NX * NX, NX, RSP, NU, LC> A;              // -> C[:, nu:]
+  Seg<double, NU * NU, NU, RSP, 0, LH> R;               // -> H[0:nu, 0:nu]
+  Seg<double, NU * NX, NX, RSP, NU, LH> S;              // -> H[0:nu, nu:]
+  Seg<double, NX * NX, NX, RSP, NU * RSP + NU, LH> Q;   // -> H[nu:, nu:]
   Seg<double, NU, NU, NU, 0, NUX> r;                    // -> RQ[0:nu]
   Seg<double, NX, NX, NX, NU, NUX> q;                   // -> RQ[nu:]
   Seg<double, NX, NX, NX, 0, NX> f;                     // -> Fv
@@ -282,10 +286,10 @@ struct StageData {
 
 template <int NX, int NU>
 __device__ __forceinline__ void zero_S_block(double* sH, const Lane& L) {
-  constexpr int NUX = NX + NU, LH = NUX * NUX;
+  constexpr int LH = Shape<NX, NU>::LH, RSP = Shape<NX, NU>::RSP;
   for (int e = L.lane; e < 4 * NU * NX; e += 64) {
     const int gg = e / (NU * NX), w = e % (NU * NX);
-    sH[gg * LH + (w / NX) * NUX + NU + (w % NX)] = 0.0;
+    sH[gg * LH + (w / NX) * RSP + NU + (w % NX)] = 0.0;
   }
 }
 
@@ -356,15 +360,16 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
     sd.store(sC, sH, sRQ, sFv, L, true);
     if (k > 0) sd.load(d, N, L, batch, k - 1, true);
     // operands of stage k from LDS
-    const double* pc = sC + g * LC + ia;          // column ia of C: pc[m * NUX]
-    const double* pr = sH + g * LH + ia * NUX;    // row ia of H
-    const double* pk = sH + g * LH + ia;          // column ia of H: pk[j * NUX]
+    constexpr int RSP = SH::RSP;
+    const double* pc = sC + g * LC + ia;          // column ia of C: pc[m * RSP]
+    const double* pr = sH + g * LH + ia * RSP;    // row ia of H
+    const double* pk = sH + g * LH + ia;          // column ia of H: pk[j * RSP]
     double c[NX];
 #pragma unroll
-    for (int m = 0; m < NX; ++m) c[m] = pc[m * NUX];
+    for (int m = 0; m < NX; ++m) c[m] = pc[m * RSP];
 #pragma unroll
     for (int j = 0; j < NUX; ++j) {
-      const double col = pk[j * NUX];
+      const double col = pk[j * RSP];
       const double v = (!isu && j < NU) ? col : 0.5 * (pr[j] + col);
       h[j] = j <= i ? v : 0.0;
     }
@@ -401,8 +406,12 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
 #pragma unroll
       for (int j = 0; j < NX; ++j) wv = fma(lq[j], t1[j], wv);
     }
+    {
+      double ta[3] = {tq, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < NX; ++m) tq = fma(c[m], bc(wv, NU + m), tq);
+      for (int m = 0; m < NX; ++m) ta[m % 3] = fma(c[m], bc(wv, NU + m), ta[m % 3]);
+      tq = ta[0] + (ta[1] + ta[2]);
+    }
     // syrk Hhat = H + V V^T
 #pragma unroll
     for (int j = 0; j < NUX; ++j) {
@@ -551,21 +560,20 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       }
     }
     if (k + 1 < N) load_fwdvec<NX, NU, TF, HS, HF>(nxt, s, k + 1, mode);
+    constexpr int RSP = SH::RSP;
     const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;          // F_k of this instance
     const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;   // F_{k+1}
-    const double* prC = s.sC + g * LC + ia;                    // column ia of C (stride NUX)
-    const double* prA = s.sC + g * LC + mi * NUX;              // row mi of C = [B row, A row]
+    const double* prC = s.sC + g * LC + ia;                    // column ia of C (stride RSP)
+    const double* prA = s.sC + g * LC + mi * RSP;              // row mi of C = [B row, A row]
 
     // t = rbar + L^S^T x on input lanes
-    double t = cur.s0, t_b = 0.0;
+    double ta[3] = {cur.s0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       const double xb = bc(xc, NU + m);
-      const double gv = (double)Fk[SH::OLS + m * NU + ic];
-      if (m & 1) t_b = fma(gv, xb, t_b);
-      else t = fma(gv, xb, t);
+      ta[m % 3] = fma((double)Fk[SH::OLS + m * NU + ic], xb, ta[m % 3]);
     }
-    t += t_b;
+    double t = ta[0] + (ta[1] + ta[2]);
     // u' = L^R^{-T} t, u = -u'
     const double dRi = (double)Fk[SH::ODR + ic];
     double uu = 0.0;
@@ -574,35 +582,36 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       const double uj = bc(t * dRi, j);
       uu = (i == j) ? uj : uu;
       const double e = (double)Fk[j * (j + 1) / 2 + ic];  // L^R[j][ic] for ic < j (in-block otherwise)
-      t = (i < j) ? fma(-e, uj, t) : t;
+      t = fma((i < j) ? -e : 0.0, uj, t);
     }
     const double du = -uu;
     // x_{k+1} = A x + B u + f on state lanes
-    double xn = cur.s0, xn_b = 0.0;
+    double xa[3] = {cur.s0, 0.0, 0.0};
 #pragma unroll
     for (int n = 0; n < NX; ++n) {
       const double xb = bc(xc, NU + n);
-      if (n & 1) xn_b = fma(prA[NU + n], xb, xn_b);
-      else xn = fma(prA[NU + n], xb, xn);
+      xa[n % 3] = fma(prA[NU + n], xb, xa[n % 3]);
     }
 #pragma unroll
-    for (int j = 0; j < NU; ++j) xn = fma(prA[j], bc(du, j), xn);
-    xn += xn_b;
-    // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}
+    for (int j = 0; j < NU; ++j) xa[(NX + j) % 3] = fma(prA[j], bc(du, j), xa[(NX + j) % 3]);
+    const double xn = xa[0] + (xa[1] + xa[2]);
+    // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}; coefficients masked to the triangle
     const TF* lqc = Fk1 + SH::OLQ + mi;                    // column mi: + m(m+1)/2
     const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;     // row mi: + j
-    double t2 = 0.0;
+    double t2a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double xb = bc(xn, NU + m);
-      t2 = (m >= mi) ? fma((double)lqc[m * (m + 1) / 2], xb, t2) : t2;
+      const double cm = (m >= mi) ? (double)lqc[m * (m + 1) / 2] : 0.0;
+      t2a[m % 3] = fma(cm, bc(xn, NU + m), t2a[m % 3]);
     }
-    double lm = cur.s1;
+    const double t2 = t2a[0] + (t2a[1] + t2a[2]);
+    double lma[3] = {cur.s1, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      const double tb = bc(t2, NU + j);
-      lm = (j <= mi) ? fma((double)lqr[j], tb, lm) : lm;
+      const double cj = (j <= mi) ? (double)lqr[j] : 0.0;
+      lma[j % 3] = fma(cj, bc(t2, NU + j), lma[j % 3]);
     }
+    const double lm = lma[0] + (lma[1] + lma[2]);
     // updated iterate
     const double unew = du + cur.zu;
     const double xnew = xn + cur.zx;
@@ -613,41 +622,39 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       s.lam[(int64_t)k * NX + mi] = lnew;
     }
     if (res) {
-      const double* hr = s.sH + g * LH + ia * NUX;   // row ia of H
-      const double* hc = s.sH + g * LH + ia;         // column ia of H (stride NUX)
+      const double* hr = s.sH + g * LH + ia * RSP;   // row ia of H
+      const double* hc = s.sH + g * LH + ia;         // column ia of H (stride RSP)
       // residual rows of stage k at the updated iterate (x_k = xk, u_k, lam_k, x_{k+1}, lam_{k-1})
-      double au = 0.0, ab = 0.0, bu = 0.0;  // S x_k + R u (input) ; B^T lam (input) / A^T lam (state)
-      double al = -xnew, bl = 0.0;          // A x_k + B u - x_{k+1} ;  A_0 x_init
-      double ax = -lkm;                     // Q x_k + S^T u - lam_{k-1} (+ A^T lam)
+      double au[2] = {0.0, 0.0};   // input lanes: S x_k ; R u
+      double ab[2] = {0.0, 0.0};   // column ia of C times lam: B^T lam (input) / A^T lam (state)
+      double al[2] = {-xnew, 0.0}; // state lanes: A x_k - x_{k+1} ; B u
+      double ax[2] = {-lkm, 0.0};  // state lanes: Q x_k - lam_{k-1} ; S^T u
 #pragma unroll
       for (int n = 0; n < NX; ++n) {
         const double xb = bc(xk, NU + n);
         const double lb = bc(lnew, NU + n);
-        const double hrow = hr[NU + n], hcol = hc[(NU + n) * NUX];
-        if (HS) au = fma(hrow, xb, au);           // input lanes: S row
-        ab = fma(prC[n * NUX], lb, ab);           // column ia of C: B^T lam (input), A^T lam (state)
-        al = fma(prA[NU + n], xb, al);            // state lanes: A row
-        ax = fma(0.5 * (hrow + hcol), xb, ax);    // state lanes: sym Q row
+        const double hrow = hr[NU + n], hcol = hc[(NU + n) * RSP];
+        if (HS) au[0] = fma(hrow, xb, au[0]);
+        ab[n & 1] = fma(prC[n * RSP], lb, ab[n & 1]);
+        al[0] = fma(prA[NU + n], xb, al[0]);
+        ax[0] = fma(0.5 * (hrow + hcol), xb, ax[0]);
       }
-      if (k == 0) {
-        bu = HS ? au : 0.0;
-        bl = al + xnew;
-      }
+      const double bu = (k == 0 && HS) ? au[0] : 0.0;   // S_0 x_init
+      const double bl = (k == 0) ? al[0] + xnew : 0.0;  // A_0 x_init
 #pragma unroll
       for (int j = 0; j < NU; ++j) {
         const double ub = bc(unew, j);
-        const double hrow = hr[j], hcol = hc[j * NUX];
-        au = fma(0.5 * (hrow + hcol), ub, au);    // input lanes: sym R row
-        al = fma(prA[j], ub, al);                 // state lanes: B row
-        if (HS) ax = fma(hcol, ub, ax);           // state lanes: S column -> S^T u
+        const double hrow = hr[j], hcol = hc[j * RSP];
+        au[1] = fma(0.5 * (hrow + hcol), ub, au[1]);
+        al[1] = fma(prA[j], ub, al[1]);
+        if (HS) ax[1] = fma(hcol, ub, ax[1]);
       }
-      au += ab;
-      ax += ab;
+      const double abt = ab[0] + ab[1];
       const double rq = s.sRQ[g * NUX + ia];
       const double fo = HF ? s.sFv[g * NX + mi] : 0.0;
-      const double rhou = -rq - au;
-      const double rhol = -fo - al;
-      const double rhox = -rq - ax;
+      const double rhou = -rq - ((au[0] + au[1]) + abt);
+      const double rhol = -fo - (al[0] + al[1]);
+      const double rhox = -rq - ((ax[0] + ax[1]) + abt);
       if (ul) {
         mr = fmax(mr, fabs(rhou));
         mb = fmax(mb, fabs(rq + bu));
@@ -743,32 +750,31 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
       rho_n = isu ? ru : rx;
       fl_n = s.flam[(int64_t)(k - 1) * NX + mi];
     }
+    constexpr int RSP = SH::RSP;
     const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;
     const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;
-    // t1 = L^Q_{k+1}^T f', w = L^Q_{k+1} t1 + p2_{k+1}
+    // t1 = L^Q_{k+1}^T f', w = L^Q_{k+1} t1 + p2_{k+1} (coefficients masked to the triangle)
     const TF* lqc = Fk1 + SH::OLQ + mi;
     const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;
-    double t1 = 0.0;
+    double t1a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double fb = bc(fl, NU + m);
-      t1 = (m >= mi) ? fma((double)lqc[m * (m + 1) / 2], fb, t1) : t1;
+      const double cm = (m >= mi) ? (double)lqc[m * (m + 1) / 2] : 0.0;
+      t1a[m % 3] = fma(cm, bc(fl, NU + m), t1a[m % 3]);
     }
-    double w = p2n;
+    const double t1 = t1a[0] + (t1a[1] + t1a[2]);
+    double wa[3] = {p2n, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      const double tb = bc(t1, NU + j);
-      w = (j <= mi) ? fma((double)lqr[j], tb, w) : w;
+      const double cj = (j <= mi) ? (double)lqr[j] : 0.0;
+      wa[j % 3] = fma(cj, bc(t1, NU + j), wa[j % 3]);
     }
+    const double w = wa[0] + (wa[1] + wa[2]);
     const double* prC = s.sC + g * LC + ia;
-    double tq = (isu || k > 0) ? -rho : 0.0, tq_b = 0.0;
+    double tqa[3] = {(isu || k > 0) ? -rho : 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < NX; ++m) {
-      const double wb = bc(w, NU + m);
-      if (m & 1) tq_b = fma(prC[m * NUX], wb, tq_b);
-      else tq = fma(prC[m * NUX], wb, tq);
-    }
-    tq += tq_b;
+    for (int m = 0; m < NX; ++m) tqa[m % 3] = fma(prC[m * RSP], bc(w, NU + m), tqa[m % 3]);
+    double tq = tqa[0] + (tqa[1] + tqa[2]);
     // input lanes: row ic of L^R (packed); state lanes: row mi of L^S
     const TF* hp = isu ? Fk + ic * (ic + 1) / 2 : Fk + SH::OLS + mi * NU;
     const double dr = (double)Fk[SH::ODR + ic];

@@ -1,0 +1,87 @@
+"""torch.autograd.Function over the C ABI: forward = lq_factor + lq_solve, backward =
+lq_solve_backward (the adjoint KKT solve with the stored factors, then the per-stage gradient
+outer products).  Uniform batches with shaped tensors:
+
+    A [B, N, nx, nx]   B [B, N, nx, nu]   Q [B, N+1, nx, nx]   R [B, N, nu, nu]
+    S [B, N, nu, nx] or None   q [B, N+1, nx]   r [B, N, nu]   f [B, N, nx] or None   x0 [B, nx]
+
+returns x [B, N, nx] (x_1..x_N), u [B, N, nu] (u_0..u_{N-1}) and lam [B, N, nx].  x and u are
+differentiable; lam is returned as a constant.
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional, Tuple
+
+import torch
+
+from . import api
+
+_PLANS: Dict[Tuple, api.Plan] = {}
+
+
+def _plan(batch, N, nx, nu, mode, device) -> api.Plan:
+    key = (batch, N, nx, nu, mode, torch.device(device).index)
+    p = _PLANS.get(key)
+    if p is None:
+        p = api.Plan(N, nx, nu, batch=batch, mode=mode)
+        _PLANS[key] = p
+    return p
+
+
+class LQSolveFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, B, Q, R, S, q, r, f, x0, mode, tol, max_it):
+        batch, N, nx, _ = A.shape
+        nu = B.shape[-1]
+        plan = _plan(batch, N, nx, nu, mode, A.device)
+        data = {"A": A, "B": B, "Q": Q, "R": R, "q": q, "r": r, "x0": x0}
+        if S is not None:
+            data["S"] = S
+        if f is not None:
+            data["f"] = f
+        data = {k: v.detach().contiguous().reshape(-1) for k, v in data.items()}
+        ws = plan.workspace(A.device)
+        info = torch.zeros(batch, dtype=torch.int32, device=A.device)
+        rel = torch.empty(batch, dtype=torch.float64, device=A.device)
+        x, u, lam = plan.empty_outputs(A.device)
+        api.factor(plan, data, ws, info)
+        api.solve(plan, data, ws, x, u, lam, rel, None, info, tol=tol, max_it=max_it)
+        ctx.save_for_backward(x, u, lam)
+        ctx.plan, ctx.data, ctx.ws, ctx.info = plan, data, ws, info
+        ctx.has_S, ctx.has_f = S is not None, f is not None
+        ctx.tol, ctx.max_it = tol, max_it
+        ctx.shapes = (batch, N, nx, nu)
+        lam_s = lam.view(batch, N, nx)
+        ctx.mark_non_differentiable(lam_s)
+        return x.view(batch, N, nx), u.view(batch, N, nu), lam_s
+
+    @staticmethod
+    def backward(ctx, gx, gu, glam):
+        x, u, lam = ctx.saved_tensors
+        batch, N, nx, nu = ctx.shapes
+        dev = x.device
+        gx = torch.zeros_like(x) if gx is None else gx.contiguous().reshape(-1)
+        gu = torch.zeros_like(u) if gu is None else gu.contiguous().reshape(-1)
+        plan = ctx.plan
+        g = {k: torch.empty(plan.totals[k], dtype=torch.float64, device=dev) for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+        if ctx.has_S:
+            g["S"] = torch.empty(plan.totals["S"], dtype=torch.float64, device=dev)
+        if ctx.has_f:
+            g["f"] = torch.empty(plan.totals["f"], dtype=torch.float64, device=dev)
+        info = ctx.info.clone()
+        api.solve_backward(plan, ctx.data, ctx.ws, x, u, lam, gx, gu, g, None, None, info, tol=ctx.tol,
+                           max_it=ctx.max_it)
+        sh = {"A": (batch, N, nx, nx), "B": (batch, N, nx, nu), "Q": (batch, N + 1, nx, nx), "R": (batch, N, nu, nu),
+              "S": (batch, N, nu, nx), "q": (batch, N + 1, nx), "r": (batch, N, nu), "f": (batch, N, nx),
+              "x0": (batch, nx)}
+        out = {k: v.view(sh[k]) for k, v in g.items()}
+        return (out["A"], out["B"], out["Q"], out["R"], out.get("S"), out["q"], out["r"], out.get("f"), out["x0"],
+                None, None, None)
+
+
+def lq_solve(A, B, Q, R, q, r, x0, S=None, f=None, mode: str = "f64", tol: float = 1e-10,
+             max_it: Optional[int] = None):
+    """Differentiable batched LQ KKT solve (see module docstring for shapes)."""
+    if max_it is None:
+        max_it = 0 if mode == "f64" else 10
+    return LQSolveFn.apply(A, B, Q, R, S, q, r, f, x0, mode, tol, max_it)

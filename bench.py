@@ -31,24 +31,53 @@ TOL = 1e-10
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_factor(batch, N, nx, nu, fbytes):
-    """Minimum HBM bytes of the factor sweep: read A, B, Q_1..Q_N, R, q_1..q_N, r once; write the
-    packed factors (L^R, L^S, L^Q lower triangles + inverse diagonals) in the storage precision and
-    the float64 backward-sweep vectors rbar_k, p_k."""
-    per_stage_in = 8 * (nx * nx + nx * nu + nx * nx + nu * nu + nx + nu)
+def stage_sizes(nx, nu):
+    """Elements per stage: input data read by a factor or residual pass, packed factor block."""
+    data = nx * nx + nx * nu + nx * nx + nu * nu + nx + nu      # A, B, Q_k, R, q_k, r
     fac = nu * (nu + 1) // 2 + nu + nx * nu + nx * (nx + 1) // 2 + nx
-    per_stage_out = fbytes * fac + 8 * (nu + nx)
-    return batch * N * (per_stage_in + per_stage_out)
+    return data, fac
 
 
-def algorithmic_bytes_solve(batch, N, nx, nu, fbytes, passes_fwd, passes_res):
-    """Minimum HBM bytes of lq_solve: each forward pass reads the factors, rbar/p, A_k, B_k and
-    writes x, u, lam; each residual pass reads all stage data and the iterate."""
-    fac = fbytes * (nu * (nu + 1) // 2 + nu + nx * nu + nx * (nx + 1) // 2 + nx)
-    z = 8 * (2 * nx + nu)
-    fwd = fac + 8 * (nu + nx) + 8 * (nx * nx + nx * nu) + z
-    res = 8 * (nx * nx + nx * nu + nx * nx + nu * nu + nx + nu) + z
-    return batch * N * (passes_fwd * fwd + passes_res * res)
+def algorithmic_bytes_factor(batch, N, nx, nu, fbytes):
+    """Minimum HBM bytes of one factor launch: read the stage data once; write the packed
+    factors (L^R, L^S, L^Q lower triangles + inverse diagonals) in the storage precision and the
+    float64 backward-sweep vectors rbar_k, p_k."""
+    data, fac = stage_sizes(nx, nu)
+    return batch * N * (8 * data + fbytes * fac + 8 * (nu + nx))
+
+
+def algorithmic_bytes_solve(N, nx, nu, fbytes, iters):
+    """Minimum HBM bytes of one solve launch of this design, summed over instances (iters = the
+    per-instance refinement iterations).  Per stage:
+      forward+residual pass: read factors, A, B, Q, R, q, r, sweep vectors (+ old iterate and
+        flam in correction passes); write x, u, lam (+ the residual when another iteration follows);
+      backward correction pass: read factors, A, B, the stored residual; write the sweep vectors."""
+    data, fac = stage_sizes(nx, nu)
+    z = 2 * nx + nu
+    total = 0
+    for it in np.asarray(iters, dtype=np.int64):
+        fwd0 = 8 * data + fbytes * fac + 8 * (nu + nx) + 8 * z + (8 * z if it > 0 else 0)
+        bwd = fbytes * fac + 8 * (nx * nx + nx * nu) + 8 * z + 8 * (nu + nx)
+        fwd1 = 8 * data + fbytes * fac + 8 * (nu + nx) + 8 * nx + 16 * z
+        total += fwd0 + it * (bwd + fwd1) + max(it - 1, 0) * 8 * z
+    return int(total) * N
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counters, if the kernel
+    source is unchanged since they were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"] or kernel not in rec["kernels"]:
+        return None
+    k = rec["kernels"][kernel]
+    return k["read_bytes"] + k["write_bytes"]
 
 
 def oracle_worker(args):
@@ -183,13 +212,19 @@ def main():
 
     # roofline of the dominant kernel of the reported (mixed) path
     it_mean = float(np.mean(m["iters"]))
-    passes_fwd = 1 + int(m["iters"].max())
-    passes_res = 1 + int(m["iters"].max())
+    names = {"factor": f"k_factor_small<{NX}, {NU}, float, float, false, false>",
+             "solve": f"k_solve_small<{NX}, {NU}, float, false, false>"}
     kern = {"factor": (m["ms_factor"], algorithmic_bytes_factor(BATCH, N, NX, NU, 4)),
-            "solve": (m["ms_solve"], algorithmic_bytes_solve(BATCH, N, NX, NU, 4, passes_fwd, passes_res))}
+            "solve": (m["ms_solve"], algorithmic_bytes_solve(N, NX, NU, 4, m["iters"]))}
     dom = max(kern, key=lambda k: kern[k][0])
     ms, by = kern[dom]
     achieved = by / (ms * 1e-3) / 1e9
+    tr = profiled_traffic(names[dom]) if m["plan"].variant == "small" else None
+    f64k = {"factor": {"ms": f["ms_factor"], "algorithmic_bytes": algorithmic_bytes_factor(BATCH, N, NX, NU, 8)},
+            "solve": {"ms": f["ms_solve"], "algorithmic_bytes": algorithmic_bytes_solve(N, NX, NU, 8, f["iters"])}}
+    for v in f64k.values():
+        v["GBps"] = v["algorithmic_bytes"] / (v["ms"] * 1e-3) / 1e9
+    mxk = {k: {"ms": v[0], "algorithmic_bytes": v[1], "GBps": v[1] / (v[0] * 1e-3) / 1e9} for k, v in kern.items()}
     out = {
         "metric": METRIC,
         "value": BATCH / (m["ms_per_step"] * 1e-3),
@@ -207,15 +242,13 @@ def main():
                    "batch": BATCH, "N": N, "nx": NX, "nu": NU, "tol": TOL, "max_it": args.max_it,
                    "variant": m["plan"].variant},
         "fp64": {"value": BATCH / (f["ms_per_step"] * 1e-3), "ms_per_step": f["ms_per_step"],
-                 "ms_factor": f["ms_factor"], "ms_solve": f["ms_solve"], "max_rel_res": float(f["rel"].max()),
-                 "oracle_rel_res_sampled": worst["f64"]},
-        "mixed": {"ms_factor": m["ms_factor"], "ms_solve": m["ms_solve"], "max_rel_res": float(m["rel"].max()),
-                  "iters_mean": it_mean, "iters_max": int(m["iters"].max()),
-                  "oracle_rel_res_sampled": worst["mixed_f32"]},
+                 "max_rel_res": float(f["rel"].max()), "oracle_rel_res_sampled": worst["f64"], "kernels": f64k},
+        "mixed": {"max_rel_res": float(m["rel"].max()), "iters_mean": it_mean, "iters_max": int(m["iters"].max()),
+                  "oracle_rel_res_sampled": worst["mixed_f32"], "kernels": mxk},
         "mixed_over_fp64": f["ms_per_step"] / m["ms_per_step"],
         "equal_residual_ok": bool(ok),
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
                      "algorithmic_bytes_per_launch": by, "ms_per_launch": ms},
         "cpu_baseline": cpu,
     }

@@ -16,6 +16,11 @@ class LqData(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("A", "B", "Q", "R", "S", "q", "r", "f", "x0")]
 
 
+class LqLaunch(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("persistent", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class LqSolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_it", C.c_int32), ("check", C.c_int32)]
 
@@ -29,6 +34,8 @@ EXPORTS = {
     "lq_plan_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "lq_plan_offsets": (C.c_int64, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
     "lq_plan_variant": (C.c_char_p, [C.c_void_p]),
+    "lq_plan_set_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lq_plan_get_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lq_factor": (C.c_int, [C.c_void_p, C.POINTER(LqData), C.c_void_p, C.c_void_p, C.c_void_p]),
     "lq_solve": (C.c_int, [C.c_void_p, C.POINTER(LqData), C.c_void_p, C.POINTER(LqSolveOpts)]
                  + [C.c_void_p] * 6 + [C.c_void_p]),

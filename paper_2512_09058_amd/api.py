@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ARRAYS, LqData, LqSolveOpts, MODES, check
+from ._lib import ARRAYS, LqData, LqLaunch, LqSolveOpts, MODES, check
 
 INPUTS = ["A", "B", "Q", "R", "S", "q", "r", "f", "x0"]
 
@@ -76,6 +76,24 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def set_launch(self, threads: int = 128, persistent: int = 0, blocks_per_cu: int = 0):
+        """Launch shape of the general-size kernels (see lq_plan_set_launch)."""
+        c = LqLaunch(int(threads), int(persistent), int(blocks_per_cu), 0)
+        check(_lib.load().lq_plan_set_launch(self._h, C.byref(c)), "lq_plan_set_launch")
+
+    def get_launch(self) -> dict:
+        c = LqLaunch()
+        check(_lib.load().lq_plan_get_launch(self._h, C.byref(c)), "lq_plan_get_launch")
+        return {"threads": c.threads, "persistent": c.persistent, "blocks_per_cu": c.blocks_per_cu}
+
+    def signature(self) -> str:
+        """Shape signature used as the autotuner's cache key."""
+        import hashlib
+        h = hashlib.sha1()
+        for a in (self.N, self.nx, self.nu):
+            h.update(np.ascontiguousarray(a, dtype=np.int32).tobytes())
+        return f"{self.mode}:{self.batch}:{h.hexdigest()[:16]}"
 
     def workspace(self, device=None) -> torch.Tensor:
         # torch's caching allocator returns 256-byte aligned blocks
@@ -157,3 +175,26 @@ def unpack(plan: Plan, name: str, flat: torch.Tensor, i: int) -> np.ndarray:
     n = int(np.prod(shp))
     o = int(plan.offsets[name][i])
     return flat[o:o + n].detach().cpu().numpy().reshape(shp)
+
+
+def capture(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, lam, rel_res=None, iters=None,
+            info=None, tol: float = 1e-10, max_it: int = 0, check_res: bool = True, warmup: int = 1):
+    """Capture lq_factor + lq_solve on a side stream into a HIP graph (torch.cuda.CUDAGraph);
+    replay() re-runs the whole sequence on the captured buffers.  The calls only enqueue kernels
+    (work counters are reset by a kernel, not a memset), so nothing else lands in the graph."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            factor(plan, data, ws, info, stream=s)
+            solve(plan, data, ws, x, u, lam, rel_res, iters, info, tol=tol, max_it=max_it, check_res=check_res,
+                  stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        st = torch.cuda.current_stream()
+        factor(plan, data, ws, info, stream=st)
+        solve(plan, data, ws, x, u, lam, rel_res, iters, info, tol=tol, max_it=max_it, check_res=check_res,
+              stream=st)
+    return g

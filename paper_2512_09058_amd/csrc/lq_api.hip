@@ -14,8 +14,11 @@ namespace lq {
 size_t generic_factor_lds(int nx, int nu);
 size_t generic_solve_lds(int nx, int nu);
 hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F,
-                                 double* V, int32_t* info, size_t lds, hipStream_t st);
-hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, hipStream_t st);
+                                 double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st);
+hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, const GenericLaunch& c,
+                                hipStream_t st);
+hipError_t prepare_generic(size_t lds_factor);
+int generic_blocks_per_cu(int threads, size_t lds, bool factor, lq_mode mode);
 hipError_t launch_grad_generic(const GradArgs& a, hipStream_t st);
 
 // Size-specialised uniform-batch kernels (lq_small.hip); return false if no variant fits.
@@ -61,7 +64,25 @@ struct lq_plan {
   size_t offF = 0, offV = 0, offV2 = 0, offZB = 0, ws_bytes = 0;
   size_t lds_factor = 0, lds_solve = 0;
   Variant variant = VAR_GENERIC;
+  int32_t* order_d = nullptr;  // device: instance indices longest first (inside the desc allocation)
+  size_t offCtr = 0;           // workspace: work counters of the persistent kernels
+  int cu_count = 0;
+  lq_launch launch = {128, 0, 0, 0};
+  int32_t grid_factor = 0, grid_solve = 0;  // persistent grid sizes for `launch`
 };
+
+// Persistent grid sizes for the plan's launch shape (host queries; done outside the calls so
+// that lq_factor / lq_solve only enqueue kernels and stay capturable in a graph).
+static void update_grids(lq_plan* p) {
+  for (int f = 0; f < 2; ++f) {
+    const size_t lds = f ? p->lds_factor : p->lds_solve;
+    int per = lq::generic_blocks_per_cu(p->launch.threads, lds, f != 0, p->mode);
+    if (p->launch.blocks_per_cu > 0 && p->launch.blocks_per_cu < per) per = p->launch.blocks_per_cu;
+    const int64_t g = (int64_t)p->cu_count * per;
+    const int32_t grid = (int32_t)(g < p->batch ? g : p->batch);
+    (f ? p->grid_factor : p->grid_solve) = grid;
+  }
+}
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -144,22 +165,76 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   p->offV = align256(p->offF + (size_t)aF * p->fbytes);
   p->offV2 = align256(p->offV + (size_t)aV * sizeof(double));
   p->offZB = align256(p->offV2 + (size_t)aV2 * sizeof(double));
-  p->ws_bytes = align256(p->offZB + (size_t)aZB * sizeof(double));
+  p->offCtr = align256(p->offZB + (size_t)aZB * sizeof(double));
+  p->ws_bytes = p->offCtr + 256;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: hipGetDevice failed");
   }
-  if (hipMalloc((void**)&p->desc_d, sizeof(Desc) * batch) != hipSuccess) {
+  hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (p->cu_count <= 0) p->cu_count = 256;
+  // longest instances first: serial Riccati operation count of each instance
+  std::vector<int32_t> order(batch);
+  std::vector<double> cost(batch);
+  for (int i = 0; i < batch; ++i) {
+    const double x = nx[i], ux = nx[i] + nu[i];
+    cost[i] = (double)N[i] * (0.5 * ux * x * x + 0.5 * ux * ux * x + ux * ux * ux / 6.0);
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a_, int32_t b_) { return cost[a_] > cost[b_]; });
+  const size_t descb = align256(sizeof(Desc) * batch);
+  if (hipMalloc((void**)&p->desc_d, descb + sizeof(int32_t) * batch) != hipSuccess) {
     delete p;
     return fail(LQ_ENOMEM, "lq_plan_create: descriptor table allocation failed");
   }
-  if (hipMemcpy(p->desc_d, p->desc_h.data(), sizeof(Desc) * batch, hipMemcpyHostToDevice) != hipSuccess) {
+  p->order_d = (int32_t*)((char*)p->desc_d + descb);
+  if (hipMemcpy(p->desc_d, p->desc_h.data(), sizeof(Desc) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->order_d, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(p->desc_d);
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: descriptor upload failed");
   }
+  if (lq::prepare_generic(ldsf) != hipSuccess && p->variant == VAR_GENERIC) {
+    hipFree(p->desc_d);
+    delete p;
+    return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve %zu bytes of LDS per workgroup", ldsf);
+  }
+  p->launch.persistent = p->uniform ? 0 : 1;
+  update_grids(p);
   *out = p;
   return LQ_OK;
+}
+
+extern "C" int lq_plan_set_launch(lq_plan* p, const lq_launch* c) {
+  g_err.clear();
+  if (!p || !c) return fail(LQ_EINVAL, "lq_plan_set_launch: plan and cfg are required");
+  if (c->threads != 64 && c->threads != 128 && c->threads != 256)
+    return fail(LQ_EINVAL, "lq_plan_set_launch: threads must be 64, 128 or 256");
+  if (c->persistent != 0 && c->persistent != 1) return fail(LQ_EINVAL, "lq_plan_set_launch: persistent is 0 or 1");
+  if (c->blocks_per_cu < 0 || c->blocks_per_cu > 64)
+    return fail(LQ_EINVAL, "lq_plan_set_launch: blocks_per_cu must be in [0, 64]");
+  p->launch = *c;
+  update_grids(p);
+  return LQ_OK;
+}
+
+extern "C" int lq_plan_get_launch(const lq_plan* p, lq_launch* c) {
+  if (!p || !c) return fail(LQ_EINVAL, "lq_plan_get_launch: plan and cfg are required");
+  *c = p->launch;
+  return LQ_OK;
+}
+
+static lq::GenericLaunch generic_launch(const lq_plan* p, void* ws, bool factor) {
+  lq::GenericLaunch c;
+  c.threads = p->launch.threads;
+  c.order = p->order_d;
+  c.counter = nullptr;
+  c.grid = p->batch;
+  if (p->launch.persistent) {
+    c.grid = factor ? p->grid_factor : p->grid_solve;
+    c.counter = (int32_t*)((char*)ws + p->offCtr) + (factor ? 0 : 1);
+  }
+  return c;
 }
 
 extern "C" void lq_plan_destroy(lq_plan* p) {
@@ -214,7 +289,8 @@ extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* 
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_factor_small(p->mode, p->batch, p->N[0], p->nx[0], p->nu[0], *d, F, V, info, st);
   else
-    e = lq::launch_factor_generic(p->mode, p->desc_d, p->batch, *d, F, V, info, p->lds_factor, st);
+    e = lq::launch_factor_generic(p->mode, p->desc_d, p->batch, *d, F, V, info, p->lds_factor,
+                                  generic_launch(p, ws, true), st);
   return launch_status(e, "lq_factor");
 }
 
@@ -258,7 +334,7 @@ extern "C" int lq_solve(const lq_plan* p, const lq_data* d, void* ws, const lq_s
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_solve_small(p->mode, p->N[0], p->nx[0], p->nu[0], a, st);
   else
-    e = lq::launch_solve_generic(p->mode, a, p->lds_solve, st);
+    e = lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
   return launch_status(e, "lq_solve");
 }
 
@@ -283,7 +359,7 @@ extern "C" int lq_solve_backward(const lq_plan* p, const lq_data* d, void* ws, c
   a.gx = gx; a.gu = gu;
   a.rhs = lq::RHS_ADJOINT;
   a.rel_res = rel_res; a.iters = iters; a.info = info;
-  hipError_t e = lq::launch_solve_generic(p->mode, a, p->lds_solve, st);
+  hipError_t e = lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
   if ((rc = launch_status(e, "lq_solve_backward"))) return rc;
   lq::GradArgs g;
   g.desc = p->desc_d; g.batch = p->batch; g.d = *d;

@@ -74,16 +74,10 @@ __device__ void potrf_lds(double* H, int ld, int n, int ncol, double* dinv, int*
   __syncthreads();
 }
 
+// Factor sweep of instance b by the whole workgroup.
 template <typename TF, typename TP>
-__global__ void __launch_bounds__(128) k_factor_generic(const Desc* __restrict__ desc, int batch,
-                                                        lq_data d, TF* __restrict__ F,
-                                                        double* __restrict__ Vws,
-                                                        int32_t* __restrict__ info) {
-  extern __shared__ double smem[];
-  __shared__ int s_bad, s_info;
-  const int b = blockIdx.x;
-  if (b >= batch) return;
-  const Desc D = desc[b];
+__device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restrict__ F, double* __restrict__ Vws,
+                           int32_t* __restrict__ info, double* smem, int& s_bad, int& s_info) {
   const int N = D.N, nx = D.nx, nu = D.nu, nux = nx + nu;
   const int tid = threadIdx.x, nt = blockDim.x;
   double* H = smem;              // nux*nux   (stage tile; also stages C = [B A])
@@ -235,6 +229,47 @@ __global__ void __launch_bounds__(128) k_factor_generic(const Desc* __restrict__
     __syncthreads();
   }
   if (tid == 0) info[b] = s_info;
+  __syncthreads();
+}
+
+// Work distribution shared by the generic kernels: without a counter, workgroup g takes the
+// instance order[g] (one workgroup per instance; the order lists instances longest first, so
+// the hardware dispatcher starts the long ones first).  With a counter, a persistent grid
+// pulls positions from it until the batch is exhausted (every workgroup exits once the counter
+// has passed batch).
+template <typename F>
+__device__ __forceinline__ void for_each_instance(int batch, const int32_t* order, int32_t* counter, F&& body) {
+  __shared__ int s_next;
+  if (counter == nullptr) {
+    const int t = blockIdx.x;
+    if (t < batch) body(order ? order[t] : t);
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_next;
+    __syncthreads();
+    if (t >= batch) break;
+    body(order ? order[t] : t);
+  }
+}
+
+template <int NT, typename TF, typename TP>
+__global__ void __launch_bounds__(NT) k_factor_generic(const Desc* __restrict__ desc, int batch, lq_data d,
+                                                       TF* __restrict__ F, double* __restrict__ Vws,
+                                                       int32_t* __restrict__ info, const int32_t* __restrict__ order,
+                                                       int32_t* counter) {
+  extern __shared__ double smem[];
+  __shared__ int s_bad, s_info;
+  for_each_instance(batch, order, counter, [&](int b) {
+    const Desc D = desc[b];
+    factor_one<TF, TP>(D, b, d, F, Vws, info, smem, s_bad, s_info);
+  });
+}
+
+__global__ void k_reset_counter(int32_t* c) {
+  if (threadIdx.x == 0) c[0] = 0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -487,11 +522,7 @@ __device__ double resid_bwd(const InstView& v, const FactView<TF>& fv, bool swee
 }
 
 template <typename TF>
-__global__ void __launch_bounds__(128) k_solve_generic(SolveArgs a, int64_t fs_unused) {
-  extern __shared__ double sm[];
-  __shared__ double red[128];
-  const int b = blockIdx.x;
-  if (b >= a.batch) return;
+__device__ void solve_one(const SolveArgs& a, int b, double* sm, double* red) {
   const Desc D = a.desc[b];
   InstView v;
   v.N = D.N; v.nx = D.nx; v.nu = D.nu;
@@ -563,6 +594,15 @@ __global__ void __launch_bounds__(128) k_solve_generic(SolveArgs a, int64_t fs_u
       }
     }
   }
+  __syncthreads();
+}
+
+template <int NT, typename TF>
+__global__ void __launch_bounds__(NT) k_solve_generic(SolveArgs a, const int32_t* __restrict__ order,
+                                                      int32_t* counter) {
+  extern __shared__ double sm[];
+  __shared__ double red[NT];
+  for_each_instance(a.batch, order, counter, [&](int b) { solve_one<TF>(a, b, sm, red); });
 }
 
 // Gradient outer products of the adjoint (one workgroup per instance).
@@ -639,27 +679,88 @@ size_t generic_factor_lds(int nx, int nu) {
 }
 size_t generic_solve_lds(int nx, int nu) { return sizeof(double) * (size_t)(7 * nx + 3 * nu + nx + nu); }
 
-hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F,
-                                 double* V, int32_t* info, size_t lds, hipStream_t st) {
-  if (mode == LQ_F64) {
-    auto k = k_factor_generic<double, double>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(batch), dim3(128), lds, st, desc, batch, d, (double*)F, V, info);
-  } else {
-    auto k = k_factor_generic<float, float>;
-    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(batch), dim3(128), lds, st, desc, batch, d, (float*)F, V, info);
-  }
+template <int NT>
+static hipError_t factor_nt(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F, double* V,
+                            int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st) {
+  const dim3 grid(c.counter ? c.grid : batch), block(NT);
+  if (mode == LQ_F64)
+    hipLaunchKernelGGL((k_factor_generic<NT, double, double>), grid, block, lds, st, desc, batch, d, (double*)F, V,
+                       info, c.order, c.counter);
+  else
+    hipLaunchKernelGGL((k_factor_generic<NT, float, float>), grid, block, lds, st, desc, batch, d, (float*)F, V,
+                       info, c.order, c.counter);
   return hipGetLastError();
 }
 
-hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, hipStream_t st) {
-  if (mode == LQ_F64) {
-    hipLaunchKernelGGL(k_solve_generic<double>, dim3(a.batch), dim3(128), lds, st, a, (int64_t)0);
-  } else {
-    hipLaunchKernelGGL(k_solve_generic<float>, dim3(a.batch), dim3(128), lds, st, a, (int64_t)0);
+hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F,
+                                 double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st) {
+  if (c.counter) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, c.counter);
   }
+  switch (c.threads) {
+    case 64: return factor_nt<64>(mode, desc, batch, d, F, V, info, lds, c, st);
+    case 256: return factor_nt<256>(mode, desc, batch, d, F, V, info, lds, c, st);
+    default: return factor_nt<128>(mode, desc, batch, d, F, V, info, lds, c, st);
+  }
+}
+
+template <int NT>
+static hipError_t solve_nt(lq_mode mode, const SolveArgs& a, size_t lds, const GenericLaunch& c, hipStream_t st) {
+  const dim3 grid(c.counter ? c.grid : a.batch), block(NT);
+  if (mode == LQ_F64)
+    hipLaunchKernelGGL((k_solve_generic<NT, double>), grid, block, lds, st, a, c.order, c.counter);
+  else
+    hipLaunchKernelGGL((k_solve_generic<NT, float>), grid, block, lds, st, a, c.order, c.counter);
   return hipGetLastError();
+}
+
+hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, const GenericLaunch& c,
+                                hipStream_t st) {
+  if (c.counter) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, c.counter);
+  }
+  switch (c.threads) {
+    case 64: return solve_nt<64>(mode, a, lds, c, st);
+    case 256: return solve_nt<256>(mode, a, lds, c, st);
+    default: return solve_nt<128>(mode, a, lds, c, st);
+  }
+}
+
+// Raise the dynamic-LDS limit of every generic factor instantiation (done once per plan, not
+// inside calls, so the calls stay capturable in a graph).
+hipError_t prepare_generic(size_t lds_factor) {
+  hipError_t e = hipSuccess;
+  const void* ks[] = {(const void*)k_factor_generic<64, double, double>, (const void*)k_factor_generic<128, double, double>,
+                      (const void*)k_factor_generic<256, double, double>, (const void*)k_factor_generic<64, float, float>,
+                      (const void*)k_factor_generic<128, float, float>, (const void*)k_factor_generic<256, float, float>};
+  for (const void* k : ks) {
+    hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_factor);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
+}
+
+// Workgroups of the generic kernels that fit on one CU at the given LDS size.
+int generic_blocks_per_cu(int threads, size_t lds, bool factor, lq_mode mode) {
+  int n = 0;
+  const void* k = nullptr;
+  if (factor) {
+    k = mode == LQ_F64 ? (threads == 64 ? (const void*)k_factor_generic<64, double, double>
+                         : threads == 256 ? (const void*)k_factor_generic<256, double, double>
+                                          : (const void*)k_factor_generic<128, double, double>)
+                       : (threads == 64 ? (const void*)k_factor_generic<64, float, float>
+                         : threads == 256 ? (const void*)k_factor_generic<256, float, float>
+                                          : (const void*)k_factor_generic<128, float, float>);
+  } else {
+    k = mode == LQ_F64 ? (threads == 64 ? (const void*)k_solve_generic<64, double>
+                         : threads == 256 ? (const void*)k_solve_generic<256, double>
+                                          : (const void*)k_solve_generic<128, double>)
+                       : (threads == 64 ? (const void*)k_solve_generic<64, float>
+                         : threads == 256 ? (const void*)k_solve_generic<256, float>
+                                          : (const void*)k_solve_generic<128, float>);
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 hipError_t launch_grad_generic(const GradArgs& a, hipStream_t st) {

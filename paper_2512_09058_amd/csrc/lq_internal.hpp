@@ -69,6 +69,16 @@ struct SolveArgs {
   int32_t* info;
 };
 
+// Launch shape of the generic kernels: threads per workgroup (64, 128 or 256); without a
+// counter one workgroup per instance in the given order, with a counter a persistent grid of
+// `grid` workgroups pulling instances from it.
+struct GenericLaunch {
+  int32_t threads;
+  int32_t grid;
+  const int32_t* order;  // device, [batch], instance indices longest first (may be NULL)
+  int32_t* counter;      // device work counter (NULL: one workgroup per instance)
+};
+
 // Gradient outer products of the adjoint.
 struct GradArgs {
   const Desc* desc;

@@ -149,6 +149,48 @@ def run_path(mode, data, steps, warmup, max_it):
             "x": x, "u": u, "lam": lam}
 
 
+def bench_uneven(args):
+    """The uneven workload (2048 instances, nx 6..64, nu 2..16, N 10..200): one persistent,
+    longest-first launch per call, launch shape chosen by the autotuner; float64 and mixed."""
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    from paper_2512_09058_amd import tune
+    from oracle import kkt
+    insts = synth.make_ragged(2048)
+    data = L.pack(insts)
+    Ns, nxs, nus = [p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts]
+    out = {"metric": "LQ KKT solves/s, uneven batch 2048 (nx 6..64, nu 2..16, N 10..200)", "unit": "solves/s",
+           "n_gpus": 1, "data": "synthetic (seeded generators of the workload)"}
+    for mode, max_it in (("f64", 0), ("mixed_f32", args.max_it)):
+        plan = L.Plan(Ns, nxs, nus, mode=mode)
+        choice = tune.tune(plan, data, max_it=max_it, reps=1)
+        ws = plan.workspace()
+        info = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
+        rel = torch.zeros(plan.batch, dtype=torch.float64, device="cuda")
+        its = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
+        x, u, lam = plan.empty_outputs()
+        g = L.api.capture(plan, data, ws, x, u, lam, rel, its, info, tol=TOL, max_it=max_it)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        relh = rel.cpu().numpy()
+        worst = max(kkt.residual(insts[i], L.unpack(plan, "x", x, i), L.unpack(plan, "u", u, i),
+                                 L.unpack(plan, "lam", lam, i))[1] for i in (0, 1023, 2047))
+        out[mode] = {"value": 2048 / (ms * 1e-3), "ms_per_step": ms, "launch": choice["launch"],
+                     "max_rel_res": float(relh.max()), "iters_max": int(its.max().item()),
+                     "info_ok": bool((info == 0).all().item()), "oracle_rel_res_sampled": worst}
+        print(f"[bench] uneven {mode}: {ms:.2f} ms/step, launch {choice['launch']}, max rel_res {relh.max():.2e}",
+              file=sys.stderr, flush=True)
+    out["value"] = out["mixed_f32"]["value"]
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +199,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-it", type=int, default=10)
+    ap.add_argument("--workload", choices=["batch4096", "uneven2048"], default="batch4096",
+                    help="uneven2048: measure the 2048-instance uneven workload instead (separate line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (scale for HBM counters)")
     args = ap.parse_args()
@@ -181,6 +225,9 @@ def main():
     import synth
     import paper_2512_09058_amd as L
     from oracle import kkt
+
+    if args.workload == "uneven2048":
+        return bench_uneven(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)

@@ -51,6 +51,7 @@ class Plan:
         self.batch = int(len(Ns))
         self.N, self.nx, self.nu = Ns, nxs, nus
         self.mode = mode
+        self.ckpt_stride = int(ckpt_stride)
         self._h = C.c_void_p()
         ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
         check(lib.lq_plan_create(self.batch, ip(Ns), ip(nxs), ip(nus), MODES[mode], int(ckpt_stride),
@@ -93,7 +94,7 @@ class Plan:
         h = hashlib.sha1()
         for a in (self.N, self.nx, self.nu):
             h.update(np.ascontiguousarray(a, dtype=np.int32).tobytes())
-        return f"{self.mode}:{self.batch}:{h.hexdigest()[:16]}"
+        return f"{self.mode}:{self.ckpt_stride}:{self.batch}:{h.hexdigest()[:16]}"
 
     def workspace(self, device=None) -> torch.Tensor:
         # torch's caching allocator returns 256-byte aligned blocks

@@ -19,21 +19,21 @@ from . import api
 _PLANS: Dict[Tuple, api.Plan] = {}
 
 
-def _plan(batch, N, nx, nu, mode, device) -> api.Plan:
-    key = (batch, N, nx, nu, mode, torch.device(device).index)
+def _plan(batch, N, nx, nu, mode, ckpt, device) -> api.Plan:
+    key = (batch, N, nx, nu, mode, ckpt, torch.device(device).index)
     p = _PLANS.get(key)
     if p is None:
-        p = api.Plan(N, nx, nu, batch=batch, mode=mode)
+        p = api.Plan(N, nx, nu, batch=batch, mode=mode, ckpt_stride=ckpt)
         _PLANS[key] = p
     return p
 
 
 class LQSolveFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, A, B, Q, R, S, q, r, f, x0, mode, tol, max_it):
+    def forward(ctx, A, B, Q, R, S, q, r, f, x0, mode, tol, max_it, ckpt):
         batch, N, nx, _ = A.shape
         nu = B.shape[-1]
-        plan = _plan(batch, N, nx, nu, mode, A.device)
+        plan = _plan(batch, N, nx, nu, mode, ckpt, A.device)
         data = {"A": A, "B": B, "Q": Q, "R": R, "q": q, "r": r, "x0": x0}
         if S is not None:
             data["S"] = S
@@ -76,12 +76,14 @@ class LQSolveFn(torch.autograd.Function):
               "x0": (batch, nx)}
         out = {k: v.view(sh[k]) for k, v in g.items()}
         return (out["A"], out["B"], out["Q"], out["R"], out.get("S"), out["q"], out["r"], out.get("f"), out["x0"],
-                None, None, None)
+                None, None, None, None)
 
 
 def lq_solve(A, B, Q, R, q, r, x0, S=None, f=None, mode: str = "f64", tol: float = 1e-10,
-             max_it: Optional[int] = None):
-    """Differentiable batched LQ KKT solve (see module docstring for shapes)."""
+             max_it: Optional[int] = None, ckpt_stride: int = 0):
+    """Differentiable batched LQ KKT solve (see module docstring for shapes).  ckpt_stride > 0
+    keeps only every ckpt_stride-th cost-to-go factor between forward and backward and recomputes
+    the rest segment by segment."""
     if max_it is None:
         max_it = 0 if mode == "f64" else 10
-    return LQSolveFn.apply(A, B, Q, R, S, q, r, f, x0, mode, tol, max_it)
+    return LQSolveFn.apply(A, B, Q, R, S, q, r, f, x0, mode, tol, max_it, int(ckpt_stride))

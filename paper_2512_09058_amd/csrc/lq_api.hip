@@ -100,7 +100,6 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   if (mode != LQ_F64 && mode != LQ_MIXED_F32 && mode != LQ_MIXED_BF16)
     return fail(LQ_EINVAL, "lq_plan_create: unknown mode %d", (int)mode);
   if (ckpt_stride < 0) return fail(LQ_EINVAL, "lq_plan_create: ckpt_stride must be >= 0");
-  if (ckpt_stride > 0) return fail(LQ_EUNSUPPORTED, "lq_plan_create: factor checkpointing is not built yet");
   lq_plan* p = new (std::nothrow) lq_plan;
   if (!p) return fail(LQ_ENOMEM, "lq_plan_create: host allocation failed");
   p->batch = batch;
@@ -145,7 +144,14 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     D.oR = p->off[LQ_ARR_R][i]; D.oS = p->off[LQ_ARR_S][i]; D.oq = p->off[LQ_ARR_q][i];
     D.or_ = p->off[LQ_ARR_r][i]; D.of = p->off[LQ_ARR_f][i]; D.ox0 = p->off[LQ_ARR_x0][i];
     D.ox = p->off[LQ_ARR_x][i]; D.ou = p->off[LQ_ARR_u][i]; D.olam = p->off[LQ_ARR_lam][i];
-    D.oF = aF; aF += (n + 1) * lq::stage_factor_elems(nx[i], nu[i]);
+    D.oF = aF;
+    if (ckpt_stride > 0) {
+      // checkpoint slots (stages 0, s, 2s, ..., N) and one segment buffer of s stage blocks
+      const int64_t s = ckpt_stride, nck = n / s + 1 + (n % s ? 1 : 0);
+      aF += (nck + s) * lq::stage_factor_elems(nx[i], nu[i]);
+    } else {
+      aF += (n + 1) * lq::stage_factor_elems(nx[i], nu[i]);
+    }
     D.oV = aV; aV += n * u + (n + 1) * x;
     D.oV2 = aV2; aV2 += lq::v2_elems(n, x, u);
     D.oZB = aZB; aZB += n * (2 * x + u);
@@ -154,11 +160,14 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   }
   for (int a = 0; a < LQ_ARR_COUNT; ++a) p->total[a] = acc[a];
   p->lds_factor = ldsf;
-  p->lds_solve = ldss;
-  p->variant = (p->uniform && lq::small_variant_available(mode, nx[0], nu[0])) ? VAR_SMALL : VAR_GENERIC;
-  if (p->variant == VAR_GENERIC && ldsf > kLdsLimit) {
+  // a checkpointed solve recomputes factor segments: its LDS holds the factor scratch too
+  p->lds_solve = ckpt_stride > 0 ? ldsf + ldss : ldss;
+  p->variant = (p->uniform && ckpt_stride == 0 && lq::small_variant_available(mode, nx[0], nu[0])) ? VAR_SMALL
+                                                                                               : VAR_GENERIC;
+  if (p->variant == VAR_GENERIC && (ldsf > kLdsLimit || p->lds_solve > kLdsLimit)) {
+    const size_t need = ldsf > p->lds_solve ? ldsf : p->lds_solve;
     delete p;
-    return fail(LQ_EUNSUPPORTED, "lq_plan_create: stage tile needs %zu bytes of LDS (limit %zu)", ldsf,
+    return fail(LQ_EUNSUPPORTED, "lq_plan_create: stage tile needs %zu bytes of LDS (limit %zu)", need,
                 kLdsLimit);
   }
   p->offF = 0;
@@ -194,7 +203,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: descriptor upload failed");
   }
-  if (lq::prepare_generic(ldsf) != hipSuccess && p->variant == VAR_GENERIC) {
+  if (lq::prepare_generic(ldsf > p->lds_solve ? ldsf : p->lds_solve) != hipSuccess && p->variant == VAR_GENERIC) {
     hipFree(p->desc_d);
     delete p;
     return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve %zu bytes of LDS per workgroup", ldsf);
@@ -230,6 +239,7 @@ static lq::GenericLaunch generic_launch(const lq_plan* p, void* ws, bool factor)
   c.order = p->order_d;
   c.counter = nullptr;
   c.grid = p->batch;
+  c.ckpt = p->ckpt;
   if (p->launch.persistent) {
     c.grid = factor ? p->grid_factor : p->grid_solve;
     c.counter = (int32_t*)((char*)ws + p->offCtr) + (factor ? 0 : 1);
@@ -307,6 +317,8 @@ static lq::SolveArgs base_args(const lq_plan* p, const lq_data* d, void* ws, con
   a.tol = o->tol;
   a.max_it = o->max_it;
   a.check = o->check;
+  a.ckpt = p->ckpt;
+  a.lds_factor_doubles = (int32_t)(p->lds_factor / sizeof(double));
   return a;
 }
 

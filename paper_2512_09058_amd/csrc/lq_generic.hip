@@ -74,10 +74,20 @@ __device__ void potrf_lds(double* H, int ld, int n, int ncol, double* dinv, int*
   __syncthreads();
 }
 
-// Factor sweep of instance b by the whole workgroup.
-template <typename TF, typename TP>
-__device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restrict__ F, double* __restrict__ Vws,
-                           int32_t* __restrict__ info, double* smem, int& s_bad, int& s_info) {
+// Checkpoint slot of stage k (k a multiple of the stride, or k = N) in an instance's factor
+// region; the segment buffer follows the slots.
+__device__ __forceinline__ int64_t ckpt_slots(int N, int s) { return N / s + 1 + (N % s ? 1 : 0); }
+__device__ __forceinline__ int64_t ckpt_slot(int k, int N, int s) { return k == N ? ckpt_slots(N, s) - 1 : k / s; }
+
+// Factor sweep of stages kb-1 down to ka of one instance by the whole workgroup, starting from
+// chol(Q_N) if kb = N, else from the stored L^Q_kb block `from`.  Stage k's block goes to
+// dst(k) (nullptr: not stored).  With `rhs`, also the backward sweep of (q, r, f) into rbar, p
+// and the pivot status into s_info.  Recomputing a range repeats exactly the arithmetic of the
+// full sweep, so it reproduces the same factors bit for bit.
+template <typename TF, typename TP, typename Dst>
+__device__ void factor_range(const Desc& D, const lq_data& d, int ka, int kb, Dst dst, const TF* from,
+                             double* __restrict__ rbar, double* __restrict__ pv, bool rhs, double* smem, int& s_bad,
+                             int& s_info) {
   const int N = D.N, nx = D.nx, nu = D.nu, nux = nx + nu;
   const int tid = threadIdx.x, nt = blockDim.x;
   double* H = smem;              // nux*nux   (stage tile; also stages C = [B A])
@@ -89,10 +99,6 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
   double* dinv = tq + nux;       // nux
   double* t1 = dinv + nux;       // nx
 
-  const int64_t fs = stage_factor_elems(nx, nu);
-  TF* Fi = F + D.oF;
-  double* rbar = Vws + D.oV;              // N*nu
-  double* pv = Vws + D.oV + (int64_t)N * nu;  // (N+1)*nx
   const double* A = d.A + D.oA;
   const double* Bm = d.B + D.oB;
   const double* Q = d.Q + D.oQ;
@@ -102,9 +108,16 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
   const double* r = d.r + D.or_;
   const double* f = d.f ? d.f + D.of : nullptr;
 
-  if (tid == 0) { s_bad = 0; s_info = 0; }
-  // ---- stage N: L^Q_N = chol(sym Q_N), p_N = q_N
-  {
+  if (tid == 0) { s_bad = 0; if (rhs) s_info = 0; }
+  if (kb < N) {
+    // L^Q_kb from its stored block
+    for (int e = tid; e < nx * nx; e += nt) {
+      const int i = e / nx, j = e % nx;
+      Lq[e] = j <= i ? (double)from[off_LQ(nx, nu) + i * (i + 1) / 2 + j] : 0.0;
+    }
+    __syncthreads();
+  } else {
+    // ---- stage N: L^Q_N = chol(sym Q_N), p_N = q_N
     const double* QN = Q + (int64_t)N * nx * nx;
     for (int e = tid; e < nx * nx; e += nt) {
       const int i = e / nx, j = e % nx;
@@ -113,20 +126,22 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
     for (int i = tid; i < nx; i += nt) pn[i] = q[(int64_t)N * nx + i];
     __syncthreads();
     potrf_lds(H, nx, nx, nx, dinv, &s_bad);
-    if (tid == 0 && s_bad) { s_info = s_bad == 2 ? LQ_INFO_NONFINITE : N + 1; s_bad = 0; }
-    TF* FN = Fi + (int64_t)N * fs;
+    if (tid == 0 && s_bad) { if (rhs) s_info = s_bad == 2 ? LQ_INFO_NONFINITE : N + 1; s_bad = 0; }
+    TF* FN = dst(N);
     for (int e = tid; e < nx * nx; e += nt) {
       const int i = e / nx, j = e % nx;
       const double v = j <= i ? rnd<TF>(H[e]) : 0.0;
       Lq[e] = v;
-      if (j <= i) FN[off_LQ(nx, nu) + i * (i + 1) / 2 + j] = (TF)v;
+      if (FN && j <= i) FN[off_LQ(nx, nu) + i * (i + 1) / 2 + j] = (TF)v;
     }
-    for (int i = tid; i < nx; i += nt) FN[off_dQ(nx, nu) + i] = (TF)dinv[i];
-    for (int i = tid; i < nx; i += nt) pv[(int64_t)N * nx + i] = pn[i];
+    if (FN)
+      for (int i = tid; i < nx; i += nt) FN[off_dQ(nx, nu) + i] = (TF)dinv[i];
+    if (rhs)
+      for (int i = tid; i < nx; i += nt) pv[(int64_t)N * nx + i] = pn[i];
     __syncthreads();
   }
 
-  for (int k = N - 1; k >= 0; --k) {
+  for (int k = kb - 1; k >= ka; --k) {
     const double* Ak = A + (int64_t)k * nx * nx;
     const double* Bk = Bm + (int64_t)k * nx * nu;
     // C = [B_k A_k] (nx x nux) staged in H with leading dimension nux
@@ -183,16 +198,17 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
     __syncthreads();
     potrf_lds(H, nux, nux, ncol, dinv, &s_bad);
     if (tid == 0 && s_bad) {
-      if (s_info == 0) s_info = s_bad == 2 ? LQ_INFO_NONFINITE : k + 1;
+      if (rhs && s_info == 0) s_info = s_bad == 2 ? LQ_INFO_NONFINITE : k + 1;
       s_bad = 0;
     }
     // round to the storage precision, store, keep L^Q_k for the next stage
-    TF* Fk = Fi + (int64_t)k * fs;
+    TF* Fk = dst(k);
     for (int e = tid; e < nux * nux; e += nt) {
       const int i = e / nux, j = e % nux;
       if (j > i || j >= ncol) continue;
       const double v = rnd<TF>(H[e]);
       H[e] = v;
+      if (!Fk) continue;
       if (i < nu) Fk[i * (i + 1) / 2 + j] = (TF)v;
       else if (j < nu) Fk[off_LS(nx, nu) + (i - nu) * nu + j] = (TF)v;
       else Fk[off_LQ(nx, nu) + (i - nu) * (i - nu + 1) / 2 + (j - nu)] = (TF)v;
@@ -200,6 +216,7 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
     for (int i = tid; i < ncol; i += nt) {
       const double v = rnd<TF>(dinv[i]);
       dinv[i] = v;
+      if (!Fk) continue;
       if (i < nu) Fk[off_dR(nx, nu) + i] = (TF)v;
       else Fk[off_dQ(nx, nu) + (i - nu)] = (TF)v;
     }
@@ -213,13 +230,14 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
       }
     }
     __syncthreads();
-    for (int i = tid; i < nu; i += nt) rbar[(int64_t)k * nu + i] = tq[i];
+    if (rhs)
+      for (int i = tid; i < nu; i += nt) rbar[(int64_t)k * nu + i] = tq[i];
     if (k > 0) {
       for (int i = tid; i < nx; i += nt) {
         double s = tq[nu + i];
         for (int j = 0; j < nu; ++j) s -= H[(nu + i) * nux + j] * tq[j];
         pn[i] = s;
-        pv[(int64_t)k * nx + i] = s;
+        if (rhs) pv[(int64_t)k * nx + i] = s;
       }
       for (int e = tid; e < nx * nx; e += nt) {
         const int i = e / nx, j = e % nx;
@@ -228,7 +246,25 @@ __device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restric
     }
     __syncthreads();
   }
-  if (tid == 0) info[b] = s_info;
+}
+
+// Full factor sweep of instance b (lq_factor): every stage block stored, or with a checkpoint
+// stride s only the blocks of stages 0, s, 2s, ... and N.
+template <typename TF, typename TP>
+__device__ void factor_one(const Desc& D, int b, const lq_data& d, TF* __restrict__ F, double* __restrict__ Vws,
+                           int32_t* __restrict__ info, int ckpt, double* smem, int& s_bad, int& s_info) {
+  const int N = D.N;
+  const int64_t fs = stage_factor_elems(D.nx, D.nu);
+  TF* Fi = F + D.oF;
+  double* rbar = Vws + D.oV;
+  double* pv = rbar + (int64_t)N * D.nu;
+  auto dst = [&](int k) -> TF* {
+    if (ckpt == 0) return Fi + (int64_t)k * fs;
+    if (k % ckpt == 0 || k == N) return Fi + ckpt_slot(k, N, ckpt) * fs;
+    return nullptr;
+  };
+  factor_range<TF, TP>(D, d, 0, N, dst, (const TF*)nullptr, rbar, pv, true, smem, s_bad, s_info);
+  if (threadIdx.x == 0) info[b] = s_info;
   __syncthreads();
 }
 
@@ -259,12 +295,12 @@ template <int NT, typename TF, typename TP>
 __global__ void __launch_bounds__(NT) k_factor_generic(const Desc* __restrict__ desc, int batch, lq_data d,
                                                        TF* __restrict__ F, double* __restrict__ Vws,
                                                        int32_t* __restrict__ info, const int32_t* __restrict__ order,
-                                                       int32_t* counter) {
+                                                       int32_t* counter, int ckpt) {
   extern __shared__ double smem[];
   __shared__ int s_bad, s_info;
   for_each_instance(batch, order, counter, [&](int b) {
     const Desc D = desc[b];
-    factor_one<TF, TP>(D, b, d, F, Vws, info, smem, s_bad, s_info);
+    factor_one<TF, TP>(D, b, d, F, Vws, info, ckpt, smem, s_bad, s_info);
   });
 }
 
@@ -298,34 +334,46 @@ __device__ __forceinline__ double rhs_x0(const InstView& v, int i) {
   return v.rhs == RHS_PRIMAL ? v.x0[i] : 0.0;
 }
 
+// Factor blocks of one instance.  Without checkpoints every stage has its block; with stride
+// s > 0 the stages of the current segment [k0, k1) live in the segment buffer and stage k1 (a
+// multiple of s, or N) in its checkpoint slot.
 template <typename TF>
 struct FactView {
   const TF* F;
   int64_t fs;
   int nx, nu;
-  __device__ double LR(int k, int i, int j) const { return (double)F[k * fs + i * (i + 1) / 2 + j]; }
-  __device__ double dR(int k, int i) const { return (double)F[k * fs + off_dR(nx, nu) + i]; }
-  __device__ double LS(int k, int i, int j) const { return (double)F[k * fs + off_LS(nx, nu) + i * nu + j]; }
-  __device__ double LQ(int k, int i, int j) const {
-    return (double)F[k * fs + off_LQ(nx, nu) + i * (i + 1) / 2 + j];
+  int N, s, k0, k1;
+  __device__ const TF* blk(int k) const {
+    if (s == 0) return F + (int64_t)k * fs;
+    if (k >= k0 && k < k1) return F + (ckpt_slots(N, s) + (k - k0)) * fs;
+    return F + ckpt_slot(k, N, s) * fs;
   }
+  __device__ double LR(int k, int i, int j) const { return (double)blk(k)[i * (i + 1) / 2 + j]; }
+  __device__ double dR(int k, int i) const { return (double)blk(k)[off_dR(nx, nu) + i]; }
+  __device__ double LS(int k, int i, int j) const { return (double)blk(k)[off_LS(nx, nu) + i * nu + j]; }
+  __device__ double LQ(int k, int i, int j) const { return (double)blk(k)[off_LQ(nx, nu) + i * (i + 1) / 2 + j]; }
 };
 
 // forward sweep; mode 0: z = result (x_0 = x_init, f = f_k);  mode 1: z += result (x_0 = 0,
 // f = flam_k from the preceding residual pass)
+__device__ void fwd_init(const InstView& v, int mode, double* sm) {
+  for (int i = threadIdx.x; i < v.nx; i += blockDim.x) sm[i] = mode == 0 ? rhs_x0(v, i) : 0.0;
+  __syncthreads();
+}
+
+// stages ka..kb-1 of the forward sweep (state x_ka in sm[0..nx), set by fwd_init or the
+// preceding range)
 template <typename TF>
 __device__ void fwd_sweep(const InstView& v, const FactView<TF>& fv, const double* rbar,
-                          const double* pv, const double* flam, int mode, double* sm) {
+                          const double* pv, const double* flam, int mode, double* sm, int ka, int kb) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int N = v.N, nx = v.nx, nu = v.nu;
+  const int nx = v.nx, nu = v.nu;
   double* xc = sm;        // nx
   double* xn = xc + nx;   // nx
   double* t = xn + nx;    // nu
   double* uu = t + nu;    // nu
   double* t2 = uu + nu;   // nx
-  for (int i = tid; i < nx; i += nt) xc[i] = mode == 0 ? rhs_x0(v, i) : 0.0;
-  __syncthreads();
-  for (int k = 0; k < N; ++k) {
+  for (int k = ka; k < kb; ++k) {
     for (int j = tid; j < nu; j += nt) {
       double s = rbar[(int64_t)k * nu + j];
       for (int i = 0; i < nx; ++i) s += fv.LS(k, i, j) * xc[i];
@@ -389,20 +437,14 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 
 // Residual of the current iterate (returns rel_res); if `sweep`, also the backward sweep of
 // the correction right-hand side into (rbar2, p2) and -rho_l into flam.
-template <typename TF>
-__device__ double resid_bwd(const InstView& v, const FactView<TF>& fv, bool sweep, double* rbar2,
-                            double* p2, double* flam, double* sm, double* red) {
+// Stage N rows of the residual (and p2_N of the correction sweep); mr, mb are per-thread maxima
+// of |rho| and |b|, carried over the ranges and reduced at the end.
+__device__ void resid_init(const InstView& v, bool sweep, double* p2, double* sm, double& mr, double& mb) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int N = v.N, nx = v.nx, nu = v.nu, nux = nx + nu;
-  double* pn = sm;          // nx   p2_{k+1}
-  double* rx = pn + nx;     // nx   rho_x,k
-  double* ru = rx + nx;     // nu   rho_u,k
-  double* rl = ru + nu;     // nx   rho_l,k
-  double* w = rl + nx;      // nx
-  double* t1 = w + nx;      // nx
-  double* tq = t1 + nx;     // nux
-  double mr = 0.0, mb = 0.0;
-  // stage N
+  const int N = v.N, nx = v.nx;
+  double* pn = sm;
+  mr = 0.0;
+  mb = 0.0;
   for (int i = tid; i < nx; i += nt) {
     const double* QN = v.Q + (int64_t)N * nx * nx;
     const double* xN = v.x + (int64_t)(N - 1) * nx;
@@ -416,7 +458,23 @@ __device__ double resid_bwd(const InstView& v, const FactView<TF>& fv, bool swee
     if (sweep) p2[(int64_t)N * nx + i] = -rho;
   }
   __syncthreads();
-  for (int k = N - 1; k >= 0; --k) {
+}
+
+// Residual rows of stages kb-1 down to ka; with `sweep`, the backward sweep of the correction
+// right-hand side into (rbar2, p2) and -rho_l into flam.
+template <typename TF>
+__device__ void resid_bwd(const InstView& v, const FactView<TF>& fv, bool sweep, double* rbar2, double* p2,
+                          double* flam, double* sm, double& mr, double& mb, int ka, int kb) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nx = v.nx, nu = v.nu, nux = nx + nu;
+  double* pn = sm;          // nx   p2_{k+1}
+  double* rx = pn + nx;     // nx   rho_x,k
+  double* ru = rx + nx;     // nu   rho_u,k
+  double* rl = ru + nu;     // nx   rho_l,k
+  double* w = rl + nx;      // nx
+  double* t1 = w + nx;      // nx
+  double* tq = t1 + nx;     // nux
+  for (int k = kb - 1; k >= ka; --k) {
     const double* Ak = v.A + (int64_t)k * nx * nx;
     const double* Bk = v.B + (int64_t)k * nx * nu;
     const double* Rk = v.R + (int64_t)k * nu * nu;
@@ -516,6 +574,9 @@ __device__ double resid_bwd(const InstView& v, const FactView<TF>& fv, bool swee
     }
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ double resid_final(double mr, double mb, double* red) {
   mr = block_max(mr, red);
   mb = block_max(mb, red);
   return mb > 0.0 ? mr / mb : mr;
@@ -543,15 +604,58 @@ __device__ void solve_one(const SolveArgs& a, int b, double* sm, double* red) {
   fv.F = (const TF*)a.F + D.oF;
   fv.fs = stage_factor_elems(D.nx, D.nu);
   fv.nx = D.nx; fv.nu = D.nu;
+  fv.N = D.N; fv.s = a.ckpt; fv.k0 = 0; fv.k1 = 0;
   const int N = D.N, nx = D.nx, nu = D.nu;
+  const int sc = a.ckpt;
   const double* rb0 = a.V + D.oV;
   const double* p0 = rb0 + (int64_t)N * nu;
   double* rb2 = a.V2 + D.oV2;
   double* p2 = rb2 + (int64_t)N * nu;
   double* flam = p2 + (int64_t)(N + 1) * nx;
+  // with checkpoints the factor-sweep scratch comes first in LDS, the solve vectors after it
+  double* fsm = sm;
+  double* ssm = sc ? sm + a.lds_factor_doubles : sm;
+  __shared__ int s_bad, s_info;
+  TF* seg = (TF*)a.F + D.oF + (sc ? ckpt_slots(N, sc) * fv.fs : 0);
+  auto recompute = [&](int k0, int k1) {  // factors of stages [k0, k1) into the segment buffer
+    fv.k0 = k0;
+    fv.k1 = k1;
+    auto dst = [&](int k) -> TF* { return (k >= k0 && k < k1) ? seg + (int64_t)(k - k0) * fv.fs : nullptr; };
+    const TF* from = (k1 < N) ? (const TF*)a.F + D.oF + ckpt_slot(k1, N, sc) * fv.fs : nullptr;
+    factor_range<TF, TF>(D, a.d, k0, k1, dst, from, nullptr, nullptr, false, fsm, s_bad, s_info);
+  };
+  // forward pass over all stages (segment by segment with checkpoints)
+  auto forward = [&](const double* rb, const double* pv, const double* fl, int mode) {
+    fwd_init(v, mode, ssm);
+    if (!sc) {
+      fwd_sweep<TF>(v, fv, rb, pv, fl, mode, ssm, 0, N);
+      return;
+    }
+    for (int k0 = 0; k0 < N; k0 += sc) {
+      const int k1 = k0 + sc < N ? k0 + sc : N;
+      recompute(k0, k1);
+      fwd_sweep<TF>(v, fv, rb, pv, fl, mode, ssm, k0, k1);
+    }
+  };
+  // residual (+ correction sweep) pass, backward over all stages
+  auto residual = [&](bool sweep) -> double {
+    double mr, mb;
+    resid_init(v, sweep, p2, ssm, mr, mb);
+    if (!sc) {
+      resid_bwd<TF>(v, fv, sweep, rb2, p2, flam, ssm, mr, mb, 0, N);
+    } else {
+      for (int k1 = N; k1 > 0;) {
+        const int k0 = ((k1 - 1) / sc) * sc;
+        if (sweep) recompute(k0, k1);
+        resid_bwd<TF>(v, fv, sweep, rb2, p2, flam, ssm, mr, mb, k0, k1);
+        k1 = k0;
+      }
+    }
+    return resid_final(mr, mb, red);
+  };
 
   if (a.rhs == RHS_PRIMAL) {
-    fwd_sweep<TF>(v, fv, rb0, p0, nullptr, 0, sm);
+    forward(rb0, p0, nullptr, 0);
   } else {
     // adjoint: backward sweep of (r, q, f) = (-gu, -gx, 0) first (lq_factor did the primal one)
     // The residual pass of the zero iterate gives exactly -rho = the right-hand side, so the
@@ -564,8 +668,8 @@ __device__ void solve_one(const SolveArgs& a, int b, double* sm, double* red) {
       for (int i = threadIdx.x; i < nu; i += blockDim.x) v.u[(int64_t)k * nu + i] = 0.0;
     }
     __syncthreads();
-    resid_bwd<TF>(v, fv, true, rb2, p2, flam, sm, red);
-    fwd_sweep<TF>(v, fv, rb2, p2, flam, 1, sm);
+    residual(true);
+    forward(rb2, p2, flam, 1);
   }
   int it = 0;
   double rel = 0.0;
@@ -573,10 +677,10 @@ __device__ void solve_one(const SolveArgs& a, int b, double* sm, double* red) {
   if (a.check || a.max_it > 0) {
     for (;;) {
       const bool more = it < a.max_it;
-      rel = resid_bwd<TF>(v, fv, more, rb2, p2, flam, sm, red);
+      rel = residual(more);
       have = true;
       if (!(rel > a.tol) || !more) break;  // converged (or NaN handled below) or out of iterations
-      fwd_sweep<TF>(v, fv, rb2, p2, flam, 1, sm);
+      forward(rb2, p2, flam, 1);
       ++it;
     }
   }
@@ -677,7 +781,7 @@ size_t generic_factor_lds(int nx, int nu) {
   const int nux = nx + nu;
   return sizeof(double) * ((size_t)nux * nux + (size_t)nx * nx + (size_t)nux * nx + 3 * nx + 2 * nux);
 }
-size_t generic_solve_lds(int nx, int nu) { return sizeof(double) * (size_t)(7 * nx + 3 * nu + nx + nu); }
+size_t generic_solve_lds(int nx, int nu) { return sizeof(double) * (size_t)(8 * nx + 4 * nu); }
 
 template <int NT>
 static hipError_t factor_nt(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F, double* V,
@@ -685,10 +789,10 @@ static hipError_t factor_nt(lq_mode mode, const Desc* desc, int batch, const lq_
   const dim3 grid(c.counter ? c.grid : batch), block(NT);
   if (mode == LQ_F64)
     hipLaunchKernelGGL((k_factor_generic<NT, double, double>), grid, block, lds, st, desc, batch, d, (double*)F, V,
-                       info, c.order, c.counter);
+                       info, c.order, c.counter, c.ckpt);
   else
     hipLaunchKernelGGL((k_factor_generic<NT, float, float>), grid, block, lds, st, desc, batch, d, (float*)F, V,
-                       info, c.order, c.counter);
+                       info, c.order, c.counter, c.ckpt);
   return hipGetLastError();
 }
 
@@ -732,7 +836,10 @@ hipError_t prepare_generic(size_t lds_factor) {
   hipError_t e = hipSuccess;
   const void* ks[] = {(const void*)k_factor_generic<64, double, double>, (const void*)k_factor_generic<128, double, double>,
                       (const void*)k_factor_generic<256, double, double>, (const void*)k_factor_generic<64, float, float>,
-                      (const void*)k_factor_generic<128, float, float>, (const void*)k_factor_generic<256, float, float>};
+                      (const void*)k_factor_generic<128, float, float>, (const void*)k_factor_generic<256, float, float>,
+                      (const void*)k_solve_generic<64, double>, (const void*)k_solve_generic<128, double>,
+                      (const void*)k_solve_generic<256, double>, (const void*)k_solve_generic<64, float>,
+                      (const void*)k_solve_generic<128, float>, (const void*)k_solve_generic<256, float>};
   for (const void* k : ks) {
     hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_factor);
     if (r != hipSuccess) e = r;

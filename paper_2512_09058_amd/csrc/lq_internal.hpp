@@ -67,6 +67,8 @@ struct SolveArgs {
   double* rel_res;
   int32_t* iters;
   int32_t* info;
+  int32_t ckpt;                // checkpoint stride of the factors (0: every stage stored)
+  int32_t lds_factor_doubles;  // with checkpoints: LDS doubles of the factor scratch
 };
 
 // Launch shape of the generic kernels: threads per workgroup (64, 128 or 256); without a
@@ -77,6 +79,7 @@ struct GenericLaunch {
   int32_t grid;
   const int32_t* order;  // device, [batch], instance indices longest first (may be NULL)
   int32_t* counter;      // device work counter (NULL: one workgroup per instance)
+  int32_t ckpt;          // checkpoint stride (factor kernel)
 };
 
 // Gradient outer products of the adjoint.

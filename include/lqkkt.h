@@ -144,8 +144,18 @@ typedef struct {
 int lq_plan_set_launch(lq_plan* plan, const lq_launch* cfg);
 int lq_plan_get_launch(const lq_plan* plan, lq_launch* cfg);
 
-/* Name of the kernel variant the plan dispatches to (static string). */
+/* Kernel variant of the factor sweep (the solve kernels follow from it):
+ *   "small"    uniform batches with nx + nu <= 16 of an instantiated shape: 16 lanes per instance
+ *   "tile"     nu <= 64 and ceil(nx/16) + ceil(nu/16) <= 10, modes LQ_F64 / LQ_MIXED_F32, no
+ *              checkpoints: one workgroup per instance, stage products and the blocked stage
+ *              Cholesky on 16x16 matrix-core tiles
+ *   "generic"  any shape whose stage tile fits in LDS (nx + nu up to about 80)
+ * A plan starts with the first of small, tile, generic that can take it.  lq_plan_variant returns
+ * the current name (static string); lq_plan_set_variant selects another one (LQ_EUNSUPPORTED if it
+ * cannot take the plan, LQ_EINVAL for an unknown name).  All variants produce the same workspace
+ * layout and agree to rounding. */
 const char* lq_plan_variant(const lq_plan* plan);
+int lq_plan_set_variant(lq_plan* plan, const char* name);
 
 /* Factor sweep (backward in time): for k = N-1..0 the stage products and the stage
  * Cholesky, storing L^R_k, L^S_k, L^Q_k in `workspace`; also the backward sweep of the

@@ -78,6 +78,12 @@ class Plan:
     def handle(self):
         return self._h
 
+    def set_variant(self, name: str):
+        """Select the factor kernel variant ("small", "tile" or "generic"; see lq_plan_set_variant)."""
+        lib = _lib.load()
+        check(lib.lq_plan_set_variant(self._h, name.encode()), "lq_plan_set_variant")
+        self.variant = lib.lq_plan_variant(self._h).decode()
+
     def set_launch(self, threads: int = 128, persistent: int = 0, blocks_per_cu: int = 0):
         """Launch shape of the general-size kernels (see lq_plan_set_launch)."""
         c = LqLaunch(int(threads), int(persistent), int(blocks_per_cu), 0)

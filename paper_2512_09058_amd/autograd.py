@@ -19,21 +19,23 @@ from . import api
 _PLANS: Dict[Tuple, api.Plan] = {}
 
 
-def _plan(batch, N, nx, nu, mode, ckpt, device) -> api.Plan:
-    key = (batch, N, nx, nu, mode, ckpt, torch.device(device).index)
+def _plan(batch, N, nx, nu, mode, ckpt, variant, device) -> api.Plan:
+    key = (batch, N, nx, nu, mode, ckpt, variant, torch.device(device).index)
     p = _PLANS.get(key)
     if p is None:
         p = api.Plan(N, nx, nu, batch=batch, mode=mode, ckpt_stride=ckpt)
+        if variant:
+            p.set_variant(variant)
         _PLANS[key] = p
     return p
 
 
 class LQSolveFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, A, B, Q, R, S, q, r, f, x0, mode, tol, max_it, ckpt):
+    def forward(ctx, A, B, Q, R, S, q, r, f, x0, mode, tol, max_it, ckpt, variant):
         batch, N, nx, _ = A.shape
         nu = B.shape[-1]
-        plan = _plan(batch, N, nx, nu, mode, ckpt, A.device)
+        plan = _plan(batch, N, nx, nu, mode, ckpt, variant, A.device)
         data = {"A": A, "B": B, "Q": Q, "R": R, "q": q, "r": r, "x0": x0}
         if S is not None:
             data["S"] = S
@@ -76,14 +78,15 @@ class LQSolveFn(torch.autograd.Function):
               "x0": (batch, nx)}
         out = {k: v.view(sh[k]) for k, v in g.items()}
         return (out["A"], out["B"], out["Q"], out["R"], out.get("S"), out["q"], out["r"], out.get("f"), out["x0"],
-                None, None, None, None)
+                None, None, None, None, None)
 
 
 def lq_solve(A, B, Q, R, q, r, x0, S=None, f=None, mode: str = "f64", tol: float = 1e-10,
-             max_it: Optional[int] = None, ckpt_stride: int = 0):
+             max_it: Optional[int] = None, ckpt_stride: int = 0, variant: Optional[str] = None):
     """Differentiable batched LQ KKT solve (see module docstring for shapes).  ckpt_stride > 0
     keeps only every ckpt_stride-th cost-to-go factor between forward and backward and recomputes
-    the rest segment by segment."""
+    the rest segment by segment.  variant selects the factor kernel ("small", "tile", "generic";
+    default: the plan's choice)."""
     if max_it is None:
         max_it = 0 if mode == "f64" else 10
-    return LQSolveFn.apply(A, B, Q, R, S, q, r, f, x0, mode, tol, max_it, int(ckpt_stride))
+    return LQSolveFn.apply(A, B, Q, R, S, q, r, f, x0, mode, tol, max_it, int(ckpt_stride), variant)

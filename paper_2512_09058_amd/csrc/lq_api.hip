@@ -27,6 +27,16 @@ bool small_aligned(const lq_data& d, const void* ws);
 hipError_t launch_factor_small(lq_mode mode, int batch, int N, int nx, int nu, const lq_data& d,
                                void* F, double* V, int32_t* info, hipStream_t st);
 hipError_t launch_solve_small(lq_mode mode, int N, int nx, int nu, const SolveArgs& a, hipStream_t st);
+
+// Matrix-core tile factor kernels (lq_tile.hip).
+int tile_max_columns();
+int tile_waves(int T);
+bool tile_mode_supported(lq_mode mode);
+size_t tile_lds_bytes(int nx, int nu, lq_mode mode);
+hipError_t prepare_tile(int waves, lq_mode mode, size_t lds);
+int tile_blocks_per_cu(int waves, lq_mode mode, size_t lds);
+hipError_t launch_factor_tile(lq_mode mode, int waves, const Desc* desc, int batch, const lq_data& d, void* F,
+                              double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st);
 }  // namespace lq
 
 using lq::Desc;
@@ -46,7 +56,7 @@ static int fail(int code, const char* fmt, ...) {
 
 static const size_t kLdsLimit = 160 * 1024;
 
-enum Variant : int32_t { VAR_GENERIC = 0, VAR_SMALL = 1 };
+enum Variant : int32_t { VAR_GENERIC = 0, VAR_SMALL = 1, VAR_TILE = 2 };
 
 struct lq_plan {
   int32_t batch = 0;
@@ -64,6 +74,9 @@ struct lq_plan {
   size_t offF = 0, offV = 0, offV2 = 0, offZB = 0, ws_bytes = 0;
   size_t lds_factor = 0, lds_solve = 0;
   Variant variant = VAR_GENERIC;
+  bool can_small = false, can_tile = false, can_generic = false;
+  int tile_waves = 0;       // wavefronts per workgroup of the tile factor kernel
+  size_t lds_tile = 0;      // its dynamic LDS bytes
   int32_t* order_d = nullptr;  // device: instance indices longest first (inside the desc allocation)
   size_t offCtr = 0;           // workspace: work counters of the persistent kernels
   int cu_count = 0;
@@ -76,7 +89,8 @@ struct lq_plan {
 static void update_grids(lq_plan* p) {
   for (int f = 0; f < 2; ++f) {
     const size_t lds = f ? p->lds_factor : p->lds_solve;
-    int per = lq::generic_blocks_per_cu(p->launch.threads, lds, f != 0, p->mode);
+    int per = (f && p->variant == VAR_TILE) ? lq::tile_blocks_per_cu(p->tile_waves, p->mode, p->lds_tile)
+                                            : lq::generic_blocks_per_cu(p->launch.threads, lds, f != 0, p->mode);
     if (p->launch.blocks_per_cu > 0 && p->launch.blocks_per_cu < per) per = p->launch.blocks_per_cu;
     const int64_t g = (int64_t)p->cu_count * per;
     const int32_t grid = (int32_t)(g < p->batch ? g : p->batch);
@@ -162,11 +176,25 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   p->lds_factor = ldsf;
   // a checkpointed solve recomputes factor segments: its LDS holds the factor scratch too
   p->lds_solve = ckpt_stride > 0 ? ldsf + ldss : ldss;
-  p->variant = (p->uniform && ckpt_stride == 0 && lq::small_variant_available(mode, nx[0], nu[0])) ? VAR_SMALL
-                                                                                               : VAR_GENERIC;
-  if (p->variant == VAR_GENERIC && (ldsf > kLdsLimit || p->lds_solve > kLdsLimit)) {
+  // kernel variants that can take this batch; the first available of small, tile, generic is used
+  int maxT = 0;
+  for (int i = 0; i < batch; ++i) maxT = std::max(maxT, (nx[i] + 15) / 16 + (nu[i] + 15) / 16);
+  p->can_small = p->uniform && ckpt_stride == 0 && lq::small_variant_available(mode, nx[0], nu[0]);
+  p->can_generic = ldsf <= kLdsLimit && p->lds_solve <= kLdsLimit && mode != LQ_MIXED_BF16;
+  if (ckpt_stride == 0 && lq::tile_mode_supported(mode) && maxT <= lq::tile_max_columns() && p->maxnu <= 64 &&
+      p->lds_solve <= kLdsLimit) {
+    p->tile_waves = lq::tile_waves(maxT);
+    size_t lt = 0;
+    for (int i = 0; i < batch; ++i) lt = std::max(lt, lq::tile_lds_bytes(nx[i], nu[i], mode));
+    p->lds_tile = lt;
+    p->can_tile = lt <= kLdsLimit;
+  }
+  p->variant = p->can_small ? VAR_SMALL : p->can_tile ? VAR_TILE : VAR_GENERIC;
+  if (p->variant == VAR_GENERIC && !p->can_generic) {
     const size_t need = ldsf > p->lds_solve ? ldsf : p->lds_solve;
     delete p;
+    if (mode == LQ_MIXED_BF16)
+      return fail(LQ_EUNSUPPORTED, "lq_plan_create: LQ_MIXED_BF16 has no kernel for these sizes");
     return fail(LQ_EUNSUPPORTED, "lq_plan_create: stage tile needs %zu bytes of LDS (limit %zu)", need,
                 kLdsLimit);
   }
@@ -203,10 +231,20 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: descriptor upload failed");
   }
-  if (lq::prepare_generic(ldsf > p->lds_solve ? ldsf : p->lds_solve) != hipSuccess && p->variant == VAR_GENERIC) {
+  // Raise the dynamic-LDS limits of the kernels the plan may use.  A refused request only removes
+  // that variant; its error is consumed here so that it does not surface at a later HIP call.
+  if (p->can_generic && lq::prepare_generic(std::max(ldsf, p->lds_solve)) != hipSuccess) {
+    (void)hipGetLastError();
+    p->can_generic = false;
+  }
+  if (p->can_tile && lq::prepare_tile(p->tile_waves, mode, p->lds_tile) != hipSuccess) {
+    (void)hipGetLastError();
+    p->can_tile = false;
+  }
+  if ((p->variant == VAR_GENERIC && !p->can_generic) || (p->variant == VAR_TILE && !p->can_tile)) {
     hipFree(p->desc_d);
     delete p;
-    return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve %zu bytes of LDS per workgroup", ldsf);
+    return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve the LDS of the selected kernel");
   }
   p->launch.persistent = p->uniform ? 0 : 1;
   update_grids(p);
@@ -266,7 +304,22 @@ extern "C" int64_t lq_plan_offsets(const lq_plan* p, lq_array which, int64_t* of
 
 extern "C" const char* lq_plan_variant(const lq_plan* p) {
   if (!p) return "";
-  return p->variant == VAR_SMALL ? "small" : "generic";
+  return p->variant == VAR_SMALL ? "small" : p->variant == VAR_TILE ? "tile" : "generic";
+}
+
+extern "C" int lq_plan_set_variant(lq_plan* p, const char* name) {
+  g_err.clear();
+  if (!p || !name) return fail(LQ_EINVAL, "lq_plan_set_variant: plan and name are required");
+  Variant v;
+  bool ok;
+  if (!strcmp(name, "small")) { v = VAR_SMALL; ok = p->can_small; }
+  else if (!strcmp(name, "tile")) { v = VAR_TILE; ok = p->can_tile; }
+  else if (!strcmp(name, "generic")) { v = VAR_GENERIC; ok = p->can_generic; }
+  else return fail(LQ_EINVAL, "lq_plan_set_variant: unknown variant '%s'", name);
+  if (!ok) return fail(LQ_EUNSUPPORTED, "lq_plan_set_variant: variant '%s' cannot take this plan", name);
+  p->variant = v;
+  update_grids(p);
+  return LQ_OK;
 }
 
 static int check_common(const lq_plan* p, const lq_data* d, void* ws, const char* fn) {
@@ -298,6 +351,9 @@ extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* 
   hipError_t e;
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_factor_small(p->mode, p->batch, p->N[0], p->nx[0], p->nu[0], *d, F, V, info, st);
+  else if (p->variant == VAR_TILE)
+    e = lq::launch_factor_tile(p->mode, p->tile_waves, p->desc_d, p->batch, *d, F, V, info, p->lds_tile,
+                               generic_launch(p, ws, true), st);
   else
     e = lq::launch_factor_generic(p->mode, p->desc_d, p->batch, *d, F, V, info, p->lds_factor,
                                   generic_launch(p, ws, true), st);

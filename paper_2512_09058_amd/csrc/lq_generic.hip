@@ -866,7 +866,10 @@ int generic_blocks_per_cu(int threads, size_t lds, bool factor, lq_mode mode) {
                          : threads == 256 ? (const void*)k_solve_generic<256, float>
                                           : (const void*)k_solve_generic<128, float>);
   }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
   return n > 0 ? n : 1;
 }
 

@@ -44,6 +44,42 @@ __host__ __device__ inline int64_t v2_rhox(int64_t N, int64_t nx, int64_t nu) {
   return 2 * N * nu + (N + 1) * nx + N * nx;
 }
 
+// LDS layout of the tile factor kernel (byte offsets) for TU input and TX state tiles of 16:
+// U^Q tiles of the state block (TX(TX+1)/2, factor type), input-pivot panels (TU x T float64
+// tiles), state-pivot panels (mixed: 2 x T float64 tiles; float64 mode keeps them in the U^Q
+// tiles), W slabs (2 x T product-type tiles, aliased with a panel region that is dead while they
+// live), the inverse of the current diagonal tile, the scratch tile of the diagonal step, vectors.
+struct TileLds {
+  int oLQB, oUP, oXP, oWS, oDI, oSC, oVec, total;
+};
+__host__ __device__ inline TileLds tile_lds(int TU, int TX, bool f64) {
+  const int T = TU + TX, tileD = 16 * 17 * 8, tileF = 16 * 20 * 4;
+  const int tileQ = f64 ? tileD : tileF, tileW = f64 ? tileD : tileF;
+  TileLds L;
+  int o = 0;
+  L.oLQB = o;
+  o += TX * (TX + 1) / 2 * tileQ;
+  if (f64) {
+    L.oUP = L.oWS = L.oXP = o;
+    const int up = TU * T * tileD, ws = 2 * T * tileW;
+    o += up > ws ? up : ws;
+  } else {
+    L.oUP = o;
+    o += TU * T * tileD;
+    L.oXP = L.oWS = o;
+    const int xp = 2 * T * tileD, ws = 2 * T * tileW;
+    o += xp > ws ? xp : ws;
+  }
+  L.oDI = o;
+  o += tileD;
+  L.oSC = o;  // scratch tile of the diagonal step (one wavefront at a time)
+  o += tileD;
+  L.oVec = o;
+  o += 8 * (48 * TX + 32 * T + 16 * TU);
+  L.total = o;
+  return L;
+}
+
 // Right-hand side selector of the solve kernels.
 enum RhsKind : int32_t { RHS_PRIMAL = 0, RHS_ADJOINT = 1 };
 

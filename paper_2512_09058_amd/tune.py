@@ -1,10 +1,12 @@
-"""Autotuner of the general-size kernels' launch shape (workgroup size, persistent grid,
-workgroups per CU) for a plan's shape signature.
+"""Autotuner of a plan's kernel variant and launch shape for its shape signature.
 
-tune(plan, data) times every candidate on the caller's data (factor + solve, best of a few
-runs), applies the fastest to the plan and records it in a JSON cache keyed by device name and
-plan signature; apply_cached(plan) reuses a recorded choice.  The cache path is the argument,
-else $LQKKT_TUNE_CACHE; without either nothing is read or written.
+Candidates are every factor-kernel variant that can take the plan (size-specialised, matrix-core
+tile, generic) and, per variant, the launch shapes it honours (workgroup size for the generic
+kernels; one workgroup per instance or a persistent grid with 1, 2 or as many workgroups per CU
+as fit).  tune(plan, data) times every candidate on the caller's data (factor + solve, best of a
+few runs), applies the fastest to the plan and records it in a JSON cache keyed by device name
+and plan signature; apply_cached(plan) reuses a recorded choice.  The cache path is the
+argument, else $LQKKT_TUNE_CACHE; without either nothing is read or written.
 """
 from __future__ import annotations
 
@@ -17,8 +19,33 @@ import torch
 
 from . import api
 
-CANDIDATES = [{"threads": t, "persistent": p, "blocks_per_cu": b}
-              for t in (64, 128, 256) for p, b in ((0, 0), (1, 0), (1, 1), (1, 2))]
+PERSISTENCE = ((0, 0), (1, 0), (1, 1), (1, 2))
+CANDIDATES = [{"threads": t, "persistent": p, "blocks_per_cu": b} for t in (64, 128, 256) for p, b in PERSISTENCE]
+
+
+def candidates(plan: api.Plan):
+    """(variant, launch) pairs the plan can run; the plan's current variant is kept."""
+    out = []
+    current = plan.variant
+    for v in ("small", "tile", "generic"):
+        try:
+            plan.set_variant(v)
+        except RuntimeError:
+            continue
+        if v == "small":
+            out.append({"variant": v, "launch": plan.get_launch()})
+        elif v == "tile":
+            out += [{"variant": v, "launch": {"threads": 128, "persistent": p, "blocks_per_cu": b}}
+                    for p, b in PERSISTENCE]
+        else:
+            out += [{"variant": v, "launch": c} for c in CANDIDATES]
+    plan.set_variant(current)
+    return out
+
+
+def _apply(plan: api.Plan, cand: Dict):
+    plan.set_variant(cand["variant"])
+    plan.set_launch(**cand["launch"])
 
 
 def _key(plan: api.Plan) -> str:
@@ -35,19 +62,19 @@ def apply_cached(plan: api.Plan, path: Optional[str] = None) -> Optional[Dict]:
         return None
     cfg = json.load(open(p)).get(_key(plan))
     if cfg:
-        plan.set_launch(**cfg["launch"])
+        _apply(plan, cfg)
     return cfg
 
 
 def tune(plan: api.Plan, data: Dict[str, torch.Tensor], tol: float = 1e-10, max_it: int = 0, reps: int = 3,
-         path: Optional[str] = None, candidates=CANDIDATES) -> Dict:
+         path: Optional[str] = None, cands=None) -> Dict:
     ws = plan.workspace()
     info = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
     rel = torch.zeros(plan.batch, dtype=torch.float64, device="cuda")
     x, u, lam = plan.empty_outputs()
     results = []
-    for c in candidates:
-        plan.set_launch(**c)
+    for c in (cands if cands is not None else candidates(plan)):
+        _apply(plan, c)
         best = float("inf")
         for _ in range(reps + 1):
             torch.cuda.synchronize()
@@ -58,9 +85,9 @@ def tune(plan: api.Plan, data: Dict[str, torch.Tensor], tol: float = 1e-10, max_
             best = min(best, time.perf_counter() - t0)
         results.append((best, c))
     results.sort(key=lambda r: r[0])
-    choice = {"launch": results[0][1], "ms": results[0][0] * 1e3,
+    choice = {"variant": results[0][1]["variant"], "launch": results[0][1]["launch"], "ms": results[0][0] * 1e3,
               "tried": [{"ms": r[0] * 1e3, **r[1]} for r in results]}
-    plan.set_launch(**choice["launch"])
+    _apply(plan, choice)
     p = _cache_path(path)
     if p:
         db = json.load(open(p)) if os.path.exists(p) else {}

@@ -18,7 +18,10 @@ from gpu_util import forward_error, instance_solution, oracle_solution, run  # n
 
 
 def _solve(b, mode, ckpt, max_it):
+    # the checkpointed solve recomputes segments with the generic factor code, so the reference
+    # without checkpoints uses the generic kernels too
     plan = L.Plan(b.N, b.nx, b.nu, batch=b.batch, mode=mode, ckpt_stride=ckpt)
+    plan.set_variant("generic")
     return run(b, mode, max_it=max_it, plan=plan)
 
 
@@ -49,7 +52,8 @@ def test_checkpointed_adjoint_is_bit_identical(mode):
         t = {k: (None if getattr(b, k) is None else
                  torch.tensor(getattr(b, k), dtype=torch.float64, device="cuda", requires_grad=True))
              for k in ("A", "B", "Q", "R", "q", "r", "x0")}
-        x, u, _ = lq_solve(t["A"], t["B"], t["Q"], t["R"], t["q"], t["r"], t["x0"], mode=mode, ckpt_stride=ckpt)
+        x, u, _ = lq_solve(t["A"], t["B"], t["Q"], t["R"], t["q"], t["r"], t["x0"], mode=mode, ckpt_stride=ckpt,
+                           variant="generic")
         (0.5 * (x.pow(2).sum() + u.pow(2).sum())).backward()
         grads.append({k: v.grad.clone() for k, v in t.items()})
     for k in grads[0]:

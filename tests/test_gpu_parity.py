@@ -161,8 +161,12 @@ def test_small_and_generic_agree():
     by a ragged plan that appends one differently sized instance)."""
     b = synth.make_batch(2, batch=8, N=20)
     extra = synth.random_problem(1, 3, 2, 1)
+    import paper_2512_09058_amd as L
     rs = run(b, "f64")
-    rg = run([b.instance(i) for i in range(8)] + [extra], "f64")
+    insts = [b.instance(i) for i in range(8)] + [extra]
+    plan = L.Plan([p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts], mode="f64")
+    plan.set_variant("generic")
+    rg = run(insts, "f64", plan=plan)
     assert rs["plan"].variant == "small" and rg["plan"].variant == "generic"
     for i in range(8):
         a = instance_solution(rs, i)

@@ -48,22 +48,28 @@ def _ragged_sample(n=48):
 
 @pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 8)])
 def test_launch_shapes_give_identical_results(mode, max_it):
+    """Every launch shape of a variant gives bit-identical results (the work of an instance does
+    not depend on where it runs); the tile and generic variants agree to rounding."""
     insts = _ragged_sample()
     print(f"case: ragged launch shapes {mode}", flush=True)
     plan = L.Plan([p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts], mode=mode)
-    assert plan.variant == "generic" and plan.get_launch()["persistent"] == 1
+    assert plan.variant == "tile" and plan.get_launch()["persistent"] == 1
     data = L.pack(insts)
-    ref = None
-    for c in tune.CANDIDATES:
-        plan.set_launch(**c)
+    refs = {}
+    for c in tune.candidates(plan):
+        plan.set_variant(c["variant"])
+        plan.set_launch(**c["launch"])
         out = _solve(plan, data, max_it)
         assert np.all(out[4] == 0), (c, out[4])
         assert out[3].max() <= 1e-10, (c, out[3].max())
-        if ref is None:
-            ref = out
-        else:
-            for a, b in zip(out[:3], ref[:3]):
-                assert torch.equal(a, b), c
+        ref = refs.setdefault(c["variant"], out)
+        for a, b in zip(out[:3], ref[:3]):
+            assert torch.equal(a, b), c
+    assert set(refs) == {"tile", "generic"}
+    for i in range(len(insts)):
+        sols = [(L.unpack(plan, "x", r[0], i), L.unpack(plan, "u", r[1], i), L.unpack(plan, "lam", r[2], i))
+                for r in refs.values()]
+        assert forward_error(sols[0], sols[1]) <= (1e-11 if mode == "f64" else 1e-8), i
 
 
 def test_ragged_matches_oracle_f64_and_mixed():
@@ -134,9 +140,9 @@ def test_autotuner_records_and_reapplies(tmp_path):
     data = L.pack(insts)
     path = str(tmp_path / "tune.json")
     choice = tune.tune(plan, data, path=path, reps=1)
-    assert choice["launch"] == plan.get_launch()
+    assert choice["launch"] == plan.get_launch() and choice["variant"] == plan.variant
     db = json.load(open(path))
-    assert len(db) == 1 and len(next(iter(db.values()))["tried"]) == len(tune.CANDIDATES)
+    assert len(db) == 1 and len(next(iter(db.values()))["tried"]) == len(tune.candidates(plan))
     other = L.Plan(plan.N, plan.nx, plan.nu, mode="f64")
     assert tune.apply_cached(other, path) is not None
-    assert other.get_launch() == choice["launch"]
+    assert other.get_launch() == choice["launch"] and other.variant == choice["variant"]

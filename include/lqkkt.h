@@ -129,11 +129,11 @@ int64_t lq_plan_offsets(const lq_plan* plan, lq_array which, int64_t* offsets_ho
 /* Launch shape of the general-size kernels (those serving ragged batches and shapes without a
  * size-specialised kernel).  Instances are always taken longest first (estimated by the serial
  * Riccati operation count of Sec. "Operation counts": N (nux nx^2/2 + nux^2 nx/2 + nux^3/6)).
- *   threads       workgroup size: 64, 128 or 256
+ *   threads       workgroup size: 64, 128, 256 or 512 (the tile factor kernel has its own)
  *   persistent    0: one workgroup per instance; 1: a persistent grid whose workgroups pull
  *                 instances from a work counter kept in the workspace
  *   blocks_per_cu persistent grid = CUs x blocks_per_cu (0: as many as fit)
- * A plan starts with {128, ragged ? 1 : 0, 0}; the autotuner (paper_2512_09058_amd.tune)
+ * A plan starts with {nx + nu > 48 ? 256 : 128, ragged ? 1 : 0, 0}; the autotuner (paper_2512_09058_amd.tune)
  * chooses per shape signature.  Calls on one workspace must not overlap (they share the counter). */
 typedef struct {
   int32_t threads;

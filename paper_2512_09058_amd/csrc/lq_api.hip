@@ -13,11 +13,12 @@
 namespace lq {
 size_t generic_factor_lds(int nx, int nu);
 size_t generic_solve_lds(int nx, int nu);
+size_t generic_stage_doubles(int nx, int nu);
 hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F,
                                  double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st);
 hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, const GenericLaunch& c,
                                 hipStream_t st);
-hipError_t prepare_generic(size_t lds_factor);
+hipError_t prepare_generic(bool factor, size_t lds);
 int generic_blocks_per_cu(int threads, size_t lds, bool factor, lq_mode mode);
 hipError_t launch_grad_generic(const GradArgs& a, hipStream_t st);
 
@@ -73,6 +74,7 @@ struct lq_plan {
   size_t fbytes = 0;  // bytes per factor element
   size_t offF = 0, offV = 0, offV2 = 0, offZB = 0, ws_bytes = 0;
   size_t lds_factor = 0, lds_solve = 0;
+  size_t stage_doubles = 0;  // staging buffer of the solve kernels
   Variant variant = VAR_GENERIC;
   bool can_small = false, can_tile = false, can_generic = false;
   int tile_waves = 0;       // wavefronts per workgroup of the tile factor kernel
@@ -171,7 +173,9 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     D.oZB = aZB; aZB += n * (2 * x + u);
     ldsf = std::max(ldsf, lq::generic_factor_lds(nx[i], nu[i]));
     ldss = std::max(ldss, lq::generic_solve_lds(nx[i], nu[i]));
+    p->stage_doubles = std::max(p->stage_doubles, lq::generic_stage_doubles(nx[i], nu[i]));
   }
+  ldss += sizeof(double) * p->stage_doubles;
   for (int a = 0; a < LQ_ARR_COUNT; ++a) p->total[a] = acc[a];
   p->lds_factor = ldsf;
   // a checkpointed solve recomputes factor segments: its LDS holds the factor scratch too
@@ -233,7 +237,14 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   }
   // Raise the dynamic-LDS limits of the kernels the plan may use.  A refused request only removes
   // that variant; its error is consumed here so that it does not surface at a later HIP call.
-  if (p->can_generic && lq::prepare_generic(std::max(ldsf, p->lds_solve)) != hipSuccess) {
+  if (lq::prepare_generic(false, p->lds_solve) != hipSuccess) {
+    (void)hipGetLastError();
+    const size_t need_solve = p->lds_solve;
+    hipFree(p->desc_d);
+    delete p;
+    return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve %zu bytes of LDS for the solve kernels", need_solve);
+  }
+  if (p->can_generic && lq::prepare_generic(true, ldsf) != hipSuccess) {
     (void)hipGetLastError();
     p->can_generic = false;
   }
@@ -247,6 +258,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve the LDS of the selected kernel");
   }
   p->launch.persistent = p->uniform ? 0 : 1;
+  p->launch.threads = p->maxnx + p->maxnu > 48 ? 256 : 128;
   update_grids(p);
   *out = p;
   return LQ_OK;
@@ -255,8 +267,8 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
 extern "C" int lq_plan_set_launch(lq_plan* p, const lq_launch* c) {
   g_err.clear();
   if (!p || !c) return fail(LQ_EINVAL, "lq_plan_set_launch: plan and cfg are required");
-  if (c->threads != 64 && c->threads != 128 && c->threads != 256)
-    return fail(LQ_EINVAL, "lq_plan_set_launch: threads must be 64, 128 or 256");
+  if (c->threads != 64 && c->threads != 128 && c->threads != 256 && c->threads != 512)
+    return fail(LQ_EINVAL, "lq_plan_set_launch: threads must be 64, 128, 256 or 512");
   if (c->persistent != 0 && c->persistent != 1) return fail(LQ_EINVAL, "lq_plan_set_launch: persistent is 0 or 1");
   if (c->blocks_per_cu < 0 || c->blocks_per_cu > 64)
     return fail(LQ_EINVAL, "lq_plan_set_launch: blocks_per_cu must be in [0, 64]");
@@ -375,6 +387,7 @@ static lq::SolveArgs base_args(const lq_plan* p, const lq_data* d, void* ws, con
   a.check = o->check;
   a.ckpt = p->ckpt;
   a.lds_factor_doubles = (int32_t)(p->lds_factor / sizeof(double));
+  a.stage_doubles = (int32_t)p->stage_doubles;
   return a;
 }
 

@@ -354,6 +354,176 @@ struct FactView {
   __device__ double LQ(int k, int i, int j) const { return (double)blk(k)[off_LQ(nx, nu) + i * (i + 1) / 2 + j]; }
 };
 
+// ---- LDS staging of the stage matrices of the solve sweeps.  A matrix (or a block of its rows)
+// is copied into LDS with coalesced loads (consecutive threads read consecutive elements; rows
+// padded to m + 1 doubles), then multiplied from there by groups of lanes per row (M x) or per
+// column (M^T v), reduced with cross-lane shuffles.  Reading rows or columns per thread straight
+// from global memory would touch a different cache line per lane.
+struct Stage {
+  double* buf;  // LDS staging buffer
+  int cap;      // capacity in doubles (>= max(nx, nu) + 1)
+};
+
+__device__ __forceinline__ int block_rows(const Stage& s, int m) {
+  const int r = s.cap / (m + 1);
+  return r < 1 ? 1 : r;
+}
+
+// Element e of a block maps to (row, column) = divmod(e, width); the unrolled copies below walk it
+// incrementally so that all loads of a batch are issued before the first store.
+struct Walk {
+  int i, j, di, dj, w;
+  __device__ Walk(int e0, int step, int width) : w(width) {
+    i = e0 / width;
+    j = e0 - i * width;
+    di = step / width;
+    dj = step - di * width;
+  }
+  __device__ void next() {
+    i += di;
+    j += dj;
+    if (j >= w) {
+      j -= w;
+      ++i;
+    }
+  }
+};
+
+constexpr int kStageUnroll = 8;
+
+// rows [r0, r0 + nr) of a row-major matrix with m columns
+template <typename T>
+__device__ void stage_dense(const Stage& s, const T* __restrict__ M, int m, int r0, int nr) {
+  const int n = nr * m, ld = m + 1, nt = blockDim.x;
+  const T* src = M + (int64_t)r0 * m;
+  Walk wk(threadIdx.x, nt, m);
+  for (int base = threadIdx.x; base < n; base += kStageUnroll * nt) {
+    T v[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int e = base + u * nt;
+      v[u] = e < n ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      if (base + u * nt < n) s.buf[wk.i * ld + wk.j] = (double)v[u];
+      wk.next();
+    }
+  }
+}
+
+// rows [r0, r0 + nr) of an n x n lower triangle stored packed by rows, zero above the diagonal
+template <typename T>
+__device__ void stage_tri(const Stage& s, const T* __restrict__ P, int n, int r0, int nr) {
+  const int ld = n + 1, nt = blockDim.x, tot = nr * n;
+  Walk wk(threadIdx.x, nt, n);
+  for (int base = threadIdx.x; base < tot; base += kStageUnroll * nt) {
+    T v[kStageUnroll];
+    Walk w2 = wk;
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int r = r0 + w2.i;
+      v[u] = (base + u * nt < tot && w2.j <= r) ? P[(int64_t)r * (r + 1) / 2 + w2.j] : T(0);
+      w2.next();
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      if (base + u * nt < tot) s.buf[wk.i * ld + wk.j] = (double)v[u];
+      wk.next();
+    }
+  }
+}
+
+// lanes per dot product of length len (a power of two dividing 64)
+__device__ __forceinline__ int dot_lanes(int len) { return len > 64 ? 16 : len > 16 ? 8 : len > 4 ? 4 : 1; }
+
+__device__ __forceinline__ double group_sum(double a, int g) {
+  for (int o = g >> 1; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  return a;
+}
+
+// out(i, sum_j M[i][j] x[j]) for the nr staged rows (m columns)
+template <typename F>
+__device__ void mv_rows(const Stage& s, int m, int nr, const double* x, F&& out) {
+  const int ld = m + 1, g = dot_lanes(m), sub = threadIdx.x & (g - 1), per = blockDim.x / g;
+  for (int i0 = 0; i0 < nr; i0 += per) {
+    const int i = i0 + threadIdx.x / g;
+    double a = 0.0;
+    if (i < nr) {
+      const double* row = s.buf + i * ld;
+      for (int j = sub; j < m; j += g) a = fma(row[j], x[j], a);
+    }
+    a = group_sum(a, g);
+    if (sub == 0 && i < nr) out(i, a);
+  }
+}
+
+// out(j, sum_i M[i][j] v[i]) over the nr staged rows, for the m columns
+template <typename F>
+__device__ void mv_cols(const Stage& s, int m, int nr, const double* v, F&& out) {
+  const int ld = m + 1, g = dot_lanes(nr), sub = threadIdx.x & (g - 1), per = blockDim.x / g;
+  for (int j0 = 0; j0 < m; j0 += per) {
+    const int j = j0 + threadIdx.x / g;
+    double a = 0.0;
+    if (j < m)
+      for (int i = sub; i < nr; i += g) a = fma(s.buf[i * ld + j], v[i], a);
+    a = group_sum(a, g);
+    if (sub == 0 && j < m) out(j, a);
+  }
+}
+
+// body(r0, nr) on each staged row block of an mr x m matrix, load(r0, nr) staging it
+template <typename Ld, typename Body>
+__device__ void for_blocks(const Stage& s, int mr, int m, Ld&& load, Body&& body) {
+  const int R = block_rows(s, m);
+  for (int r0 = 0; r0 < mr; r0 += R) {
+    const int nr = mr - r0 < R ? mr - r0 : R;
+    __syncthreads();
+    load(r0, nr);
+    __syncthreads();
+    body(r0, nr);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Triangular solves with the staged L^R (nu x nu, leading dimension nu + 1) and its reciprocal
+// diagonal dr: y = (L^R)^{-T} t (TRANS) or y = (L^R)^{-1} t.  Wavefront 0; for nu <= 64 lane j
+// keeps entry j and step i publishes y_i with a lane read, otherwise the entries stay in LDS.
+template <bool TRANS>
+__device__ void tri_solve(const Stage& s, int nu, const double* dr, double* t, double* y) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x, ld = nu + 1;
+  if (nu <= 64) {
+    double a = lane < nu ? t[lane] : 0.0;
+    for (int st = 0; st < nu; ++st) {
+      const int i = TRANS ? nu - 1 - st : st;
+      const double yi = readlane_d(a, i) * dr[i];
+      if (lane == 0) y[i] = yi;
+      const bool upd = TRANS ? lane < i : (lane > i && lane < nu);
+      if (upd) a = fma(-(TRANS ? s.buf[i * ld + lane] : s.buf[lane * ld + i]), yi, a);
+    }
+  } else {
+    for (int st = 0; st < nu; ++st) {
+      const int i = TRANS ? nu - 1 - st : st;
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      __builtin_amdgcn_wave_barrier();
+      const double yi = t[i] * dr[i];
+      if (lane == 0) y[i] = yi;
+      if (TRANS) {
+        for (int j = lane; j < i; j += 64) t[j] = fma(-s.buf[i * ld + j], yi, t[j]);
+      } else {
+        for (int j = i + 1 + lane; j < nu; j += 64) t[j] = fma(-s.buf[j * ld + i], yi, t[j]);
+      }
+    }
+  }
+}
+
 // forward sweep; mode 0: z = result (x_0 = x_init, f = f_k);  mode 1: z += result (x_0 = 0,
 // f = flam_k from the preceding residual pass)
 __device__ void fwd_init(const InstView& v, int mode, double* sm) {
@@ -364,59 +534,81 @@ __device__ void fwd_init(const InstView& v, int mode, double* sm) {
 // stages ka..kb-1 of the forward sweep (state x_ka in sm[0..nx), set by fwd_init or the
 // preceding range)
 template <typename TF>
-__device__ void fwd_sweep(const InstView& v, const FactView<TF>& fv, const double* rbar,
-                          const double* pv, const double* flam, int mode, double* sm, int ka, int kb) {
+__device__ void fwd_sweep(const InstView& v, const FactView<TF>& fv, const double* rbar, const double* pv,
+                          const double* flam, int mode, double* sm, const Stage& st, int ka, int kb) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nx = v.nx, nu = v.nu;
-  double* xc = sm;        // nx
-  double* xn = xc + nx;   // nx
+  double* xc = sm;        // nx   x_k
+  double* xn = xc + nx;   // nx   x_{k+1}
   double* t = xn + nx;    // nu
-  double* uu = t + nu;    // nu
+  double* uu = t + nu;    // nu   u_k
   double* t2 = uu + nu;   // nx
+  double* dr = t2 + nx;   // nu   1 / diag L^R_k
   for (int k = ka; k < kb; ++k) {
+    const TF* blk = fv.blk(k);
+    const TF* blk1 = fv.blk(k + 1);
     for (int j = tid; j < nu; j += nt) {
-      double s = rbar[(int64_t)k * nu + j];
-      for (int i = 0; i < nx; ++i) s += fv.LS(k, i, j) * xc[i];
-      t[j] = s;
+      t[j] = rbar[(int64_t)k * nu + j];
+      dr[j] = (double)blk[off_dR(nx, nu) + j];
     }
-    __syncthreads();
-    if (tid == 0) {
+    for (int i = tid; i < nx; i += nt) {
+      xn[i] = mode == 0 ? rhs_f(v, k, i) : flam[(int64_t)k * nx + i];
+      t2[i] = 0.0;
+    }
+    // t = rbar_k + (L^S_k)^T x_k
+    for_blocks(
+        st, nx, nu, [&](int r0, int nr) { stage_dense(st, blk + off_LS(nx, nu), nu, r0, nr); },
+        [&](int r0, int nr) { mv_cols(st, nu, nr, xc + r0, [&](int j, double a) { t[j] += a; }); });
+    // u_k = -(L^R_k)^{-T} t
+    for_blocks(
+        st, nu, nu, [&](int r0, int nr) { stage_tri(st, blk, nu, r0, nr); },
+        [&](int r0, int nr) {
+          if (nr == nu) tri_solve<true>(st, nu, dr, t, uu);
+        });
+    if (block_rows(st, nu) < nu && tid == 0) {  // L^R larger than the staging buffer
       for (int j = nu - 1; j >= 0; --j) {
-        double s = t[j];
-        for (int i = j + 1; i < nu; ++i) s -= fv.LR(k, i, j) * uu[i];
-        uu[j] = s * fv.dR(k, j);
+        double a = t[j];
+        for (int i = j + 1; i < nu; ++i) a -= fv.LR(k, i, j) * uu[i];
+        uu[j] = a * dr[j];
       }
-      for (int j = 0; j < nu; ++j) uu[j] = -uu[j];
     }
     __syncthreads();
+    for (int j = tid; j < nu; j += nt) uu[j] = -uu[j];
+    // x_{k+1} = A_k x_k + B_k u_k + f_k
     const double* Ak = v.A + (int64_t)k * nx * nx;
     const double* Bk = v.B + (int64_t)k * nx * nu;
-    for (int i = tid; i < nx; i += nt) {
-      double s = mode == 0 ? rhs_f(v, k, i) : flam[(int64_t)k * nx + i];
-      for (int m = 0; m < nx; ++m) s += Ak[i * nx + m] * xc[m];
-      for (int m = 0; m < nu; ++m) s += Bk[i * nu + m] * uu[m];
-      xn[i] = s;
-    }
-    __syncthreads();
-    for (int j = tid; j < nx; j += nt) {
-      double s = 0.0;
-      for (int i = j; i < nx; ++i) s += fv.LQ(k + 1, i, j) * xn[i];
-      t2[j] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < nx; i += nt) {
-      double s = pv[(int64_t)(k + 1) * nx + i];
-      for (int j = 0; j <= i; ++j) s += fv.LQ(k + 1, i, j) * t2[j];
-      double* lk = v.lam + (int64_t)k * nx;
-      double* xk = v.x + (int64_t)k * nx;
-      if (mode == 0) { lk[i] = s; xk[i] = xn[i]; }
-      else { lk[i] += s; xk[i] += xn[i]; }
+    for_blocks(
+        st, nx, nx, [&](int r0, int nr) { stage_dense(st, Ak, nx, r0, nr); },
+        [&](int r0, int nr) { mv_rows(st, nx, nr, xc, [&](int i, double a) { xn[r0 + i] += a; }); });
+    for_blocks(
+        st, nx, nu, [&](int r0, int nr) { stage_dense(st, Bk, nu, r0, nr); },
+        [&](int r0, int nr) { mv_rows(st, nu, nr, uu, [&](int i, double a) { xn[r0 + i] += a; }); });
+    // lam_k = L^Q_{k+1} (L^Q_{k+1})^T x_{k+1} + p_{k+1}
+    const TF* LQ1 = blk1 + off_LQ(nx, nu);
+    const bool one = block_rows(st, nx) >= nx;
+    for_blocks(
+        st, nx, nx, [&](int r0, int nr) { stage_tri(st, LQ1, nx, r0, nr); },
+        [&](int r0, int nr) { mv_cols(st, nx, nr, xn + r0, [&](int j, double a) { t2[j] += a; }); });
+    double* lk = v.lam + (int64_t)k * nx;
+    double* xk = v.x + (int64_t)k * nx;
+    auto emit = [&](int i, double a) {
+      const double l = pv[(int64_t)(k + 1) * nx + i] + a;
+      if (mode == 0) { lk[i] = l; xk[i] = xn[i]; }
+      else { lk[i] += l; xk[i] += xn[i]; }
+    };
+    if (one) {
+      mv_rows(st, nx, nx, t2, emit);
+    } else {
+      for_blocks(
+          st, nx, nx, [&](int r0, int nr) { stage_tri(st, LQ1, nx, r0, nr); },
+          [&](int r0, int nr) { mv_rows(st, nx, nr, t2, [&](int i, double a) { emit(r0 + i, a); }); });
     }
     for (int j = tid; j < nu; j += nt) {
       double* uk = v.u + (int64_t)k * nu;
       if (mode == 0) uk[j] = uu[j];
       else uk[j] += uu[j];
     }
+    __syncthreads();
     for (int i = tid; i < nx; i += nt) xc[i] = xn[i];
     __syncthreads();
   }
@@ -435,23 +627,36 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
-// Residual of the current iterate (returns rel_res); if `sweep`, also the backward sweep of
-// the correction right-hand side into (rbar2, p2) and -rho_l into flam.
+// Symmetric-part product: acc += 1/2 (M + M^T) x over the staged rows of an n x n matrix.
+__device__ void mv_sym(const Stage& s, int n, int r0, int nr, const double* x, double* acc) {
+  mv_rows(s, n, nr, x, [&](int i, double a) { acc[r0 + i] += 0.5 * a; });
+  __syncthreads();
+  mv_cols(s, n, nr, x + r0, [&](int j, double a) { acc[j] += 0.5 * a; });
+}
+
 // Stage N rows of the residual (and p2_N of the correction sweep); mr, mb are per-thread maxima
 // of |rho| and |b|, carried over the ranges and reduced at the end.
-__device__ void resid_init(const InstView& v, bool sweep, double* p2, double* sm, double& mr, double& mb) {
+__device__ void resid_init(const InstView& v, bool sweep, double* p2, double* sm, const Stage& st, double& mr,
+                           double& mb) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int N = v.N, nx = v.nx;
-  double* pn = sm;
+  double* pn = sm;        // nx
+  double* ax = pn + nx;   // nx
+  double* xk = ax + nx;   // nx
   mr = 0.0;
   mb = 0.0;
+  const double* xN = v.x + (int64_t)(N - 1) * nx;
   for (int i = tid; i < nx; i += nt) {
-    const double* QN = v.Q + (int64_t)N * nx * nx;
-    const double* xN = v.x + (int64_t)(N - 1) * nx;
-    double s = 0.0;
-    for (int j = 0; j < nx; ++j) s += 0.5 * (QN[i * nx + j] + QN[j * nx + i]) * xN[j];
+    ax[i] = 0.0;
+    xk[i] = xN[i];
+  }
+  const double* QN = v.Q + (int64_t)N * nx * nx;
+  for_blocks(
+      st, nx, nx, [&](int r0, int nr) { stage_dense(st, QN, nx, r0, nr); },
+      [&](int r0, int nr) { mv_sym(st, nx, r0, nr, xk, ax); });
+  for (int i = tid; i < nx; i += nt) {
     const double qi = rhs_q(v, N, i);
-    const double rho = -qi - (s - v.lam[(int64_t)(N - 1) * nx + i]);
+    const double rho = -qi - (ax[i] - v.lam[(int64_t)(N - 1) * nx + i]);
     mr = fmax(mr, fabs(rho));
     mb = fmax(mb, fabs(qi));
     pn[i] = -rho;
@@ -464,115 +669,140 @@ __device__ void resid_init(const InstView& v, bool sweep, double* p2, double* sm
 // right-hand side into (rbar2, p2) and -rho_l into flam.
 template <typename TF>
 __device__ void resid_bwd(const InstView& v, const FactView<TF>& fv, bool sweep, double* rbar2, double* p2,
-                          double* flam, double* sm, double& mr, double& mb, int ka, int kb) {
+                          double* flam, double* sm, const Stage& st, double& mr, double& mb, int ka, int kb) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int nx = v.nx, nu = v.nu, nux = nx + nu;
+  const int nx = v.nx, nu = v.nu;
   double* pn = sm;          // nx   p2_{k+1}
-  double* rx = pn + nx;     // nx   rho_x,k
-  double* ru = rx + nx;     // nu   rho_u,k
-  double* rl = ru + nu;     // nx   rho_l,k
-  double* w = rl + nx;      // nx
+  double* au = pn + nx;     // nu   R_sym u + S x_k + B^T lam_k
+  double* al = au + nu;     // nx   A x_k + B u
+  double* ax = al + nx;     // nx   S^T u + Q_sym x_k + A^T lam_k
+  double* a0 = ax + nx;     // nx   A x_k (k = 0: part of b)
+  double* s0 = a0 + nx;     // nu   S x_k (k = 0: part of b)
+  double* xk = s0 + nu;     // nx
+  double* uk = xk + nx;     // nu
+  double* lk = uk + nu;     // nx
+  double* w = lk + nx;      // nx   correction: -rho_l, then w
   double* t1 = w + nx;      // nx
-  double* tq = t1 + nx;     // nux
+  double* tq = t1 + nx;     // nux  (rhat, qhat)
+  double* dr = tq + nx + nu;  // nu  1 / diag L^R_k
+  double* yb = dr + nu;     // nu   rbar2_k
   for (int k = kb - 1; k >= ka; --k) {
     const double* Ak = v.A + (int64_t)k * nx * nx;
     const double* Bk = v.B + (int64_t)k * nx * nu;
     const double* Rk = v.R + (int64_t)k * nu * nu;
     const double* Qk = v.Q + (int64_t)k * nx * nx;
     const double* Sk = v.S ? v.S + (int64_t)k * nu * nx : nullptr;
-    const double* xk = k > 0 ? v.x + (int64_t)(k - 1) * nx : nullptr;  // x_k (k >= 1)
-    const double* xk1 = v.x + (int64_t)k * nx;                         // x_{k+1}
-    const double* uk = v.u + (int64_t)k * nu;
-    const double* lk = v.lam + (int64_t)k * nx;
-    const double* lkm = k > 0 ? v.lam + (int64_t)(k - 1) * nx : nullptr;
-#define XK(m) (k > 0 ? xk[m] : rhs_x0(v, m))
+    for (int i = tid; i < nx; i += nt) {
+      xk[i] = k > 0 ? v.x[(int64_t)(k - 1) * nx + i] : rhs_x0(v, i);
+      lk[i] = v.lam[(int64_t)k * nx + i];
+      al[i] = 0.0;
+      ax[i] = 0.0;
+      a0[i] = 0.0;
+      t1[i] = 0.0;
+    }
+    for (int j = tid; j < nu; j += nt) {
+      uk[j] = v.u[(int64_t)k * nu + j];
+      au[j] = 0.0;
+      s0[j] = 0.0;
+    }
+    for_blocks(
+        st, nu, nu, [&](int r0, int nr) { stage_dense(st, Rk, nu, r0, nr); },
+        [&](int r0, int nr) { mv_sym(st, nu, r0, nr, uk, au); });
+    if (Sk)
+      for_blocks(
+          st, nu, nx, [&](int r0, int nr) { stage_dense(st, Sk, nx, r0, nr); },
+          [&](int r0, int nr) {
+            mv_rows(st, nx, nr, xk, [&](int i, double a) { au[r0 + i] += a; s0[r0 + i] = a; });
+            mv_cols(st, nx, nr, uk + r0, [&](int j, double a) { ax[j] += a; });
+          });
+    for_blocks(
+        st, nx, nu, [&](int r0, int nr) { stage_dense(st, Bk, nu, r0, nr); },
+        [&](int r0, int nr) {
+          mv_rows(st, nu, nr, uk, [&](int i, double a) { al[r0 + i] += a; });
+          mv_cols(st, nu, nr, lk + r0, [&](int j, double a) { au[j] += a; });
+        });
+    for_blocks(
+        st, nx, nx, [&](int r0, int nr) { stage_dense(st, Ak, nx, r0, nr); },
+        [&](int r0, int nr) {
+          mv_rows(st, nx, nr, xk, [&](int i, double a) { al[r0 + i] += a; a0[r0 + i] = a; });
+          mv_cols(st, nx, nr, lk + r0, [&](int j, double a) { ax[j] += a; });
+        });
+    if (k > 0)
+      for_blocks(
+          st, nx, nx, [&](int r0, int nr) { stage_dense(st, Qk, nx, r0, nr); },
+          [&](int r0, int nr) { mv_sym(st, nx, r0, nr, xk, ax); });
+    // residual rows of stage k
     for (int i = tid; i < nu; i += nt) {
-      double s = 0.0, sb = 0.0;
-      for (int j = 0; j < nu; ++j) s += 0.5 * (Rk[i * nu + j] + Rk[j * nu + i]) * uk[j];
-      if (Sk)
-        for (int m = 0; m < nx; ++m) {
-          s += Sk[i * nx + m] * XK(m);
-          if (k == 0) sb += Sk[i * nx + m] * XK(m);
-        }
-      for (int m = 0; m < nx; ++m) s += Bk[m * nu + i] * lk[m];
       const double ri = rhs_r(v, k, i);
-      const double rho = -ri - s;
-      ru[i] = rho;
+      const double rho = -ri - au[i];
+      au[i] = -rho;  // correction right-hand side r = -rho_u
       mr = fmax(mr, fabs(rho));
-      mb = fmax(mb, fabs(ri + sb));
+      mb = fmax(mb, fabs(ri + (k == 0 ? s0[i] : 0.0)));
     }
     for (int i = tid; i < nx; i += nt) {
-      double s = -xk1[i], sb = 0.0;
-      for (int m = 0; m < nx; ++m) {
-        s += Ak[i * nx + m] * XK(m);
-        if (k == 0) sb += Ak[i * nx + m] * XK(m);
-      }
-      for (int m = 0; m < nu; ++m) s += Bk[i * nu + m] * uk[m];
       const double fi = rhs_f(v, k, i);
-      const double rho = -fi - s;
-      rl[i] = rho;
+      const double rho = -fi - (al[i] - v.x[(int64_t)k * nx + i]);
       mr = fmax(mr, fabs(rho));
-      mb = fmax(mb, fabs(fi + sb));
+      mb = fmax(mb, fabs(fi + (k == 0 ? a0[i] : 0.0)));
+      w[i] = -rho;
       if (k > 0) {
-        double s2 = -lkm[i];
-        if (Sk)
-          for (int j = 0; j < nu; ++j) s2 += Sk[j * nx + i] * uk[j];
-        for (int m = 0; m < nx; ++m) s2 += 0.5 * (Qk[i * nx + m] + Qk[m * nx + i]) * xk[m];
-        for (int m = 0; m < nx; ++m) s2 += Ak[m * nx + i] * lk[m];
         const double qi = rhs_q(v, k, i);
-        const double rho2 = -qi - s2;
-        rx[i] = rho2;
+        const double rho2 = -qi - (ax[i] - v.lam[(int64_t)(k - 1) * nx + i]);
         mr = fmax(mr, fabs(rho2));
         mb = fmax(mb, fabs(qi));
+        ax[i] = -rho2;  // q = -rho_x
       }
     }
-#undef XK
     __syncthreads();
-    if (sweep) {
-      // correction right-hand side: r = -rho_u, q = -rho_x, f = -rho_l, x_init = 0
-      for (int i = tid; i < nx; i += nt) flam[(int64_t)k * nx + i] = -rl[i];
-      for (int j = tid; j < nx; j += nt) {
-        double s = 0.0;
-        for (int m = j; m < nx; ++m) s += fv.LQ(k + 1, m, j) * (-rl[m]);
-        t1[j] = s;
+    if (!sweep) continue;
+    // correction right-hand side: r = -rho_u (au), q = -rho_x (ax), f = -rho_l (w), x_init = 0
+    const TF* blk = fv.blk(k);
+    const TF* LQ1 = fv.blk(k + 1) + off_LQ(nx, nu);
+    for (int i = tid; i < nx; i += nt) flam[(int64_t)k * nx + i] = w[i];
+    for (int j = tid; j < nu; j += nt) dr[j] = (double)blk[off_dR(nx, nu) + j];
+    // t1 = (L^Q_{k+1})^T f, then w = L^Q_{k+1} t1 + p2_{k+1}
+    for_blocks(
+        st, nx, nx, [&](int r0, int nr) { stage_tri(st, LQ1, nx, r0, nr); },
+        [&](int r0, int nr) { mv_cols(st, nx, nr, w + r0, [&](int j, double a) { t1[j] += a; }); });
+    for_blocks(
+        st, nx, nx, [&](int r0, int nr) { stage_tri(st, LQ1, nx, r0, nr); },
+        [&](int r0, int nr) { mv_rows(st, nx, nr, t1, [&](int i, double a) { w[r0 + i] = pn[r0 + i] + a; }); });
+    // (rhat, qhat) = (r, q) + [B A]^T w
+    for (int j = tid; j < nu; j += nt) tq[j] = au[j];
+    for (int i = tid; i < nx; i += nt) tq[nu + i] = k > 0 ? ax[i] : 0.0;
+    for_blocks(
+        st, nx, nu, [&](int r0, int nr) { stage_dense(st, Bk, nu, r0, nr); },
+        [&](int r0, int nr) { mv_cols(st, nu, nr, w + r0, [&](int j, double a) { tq[j] += a; }); });
+    for_blocks(
+        st, nx, nx, [&](int r0, int nr) { stage_dense(st, Ak, nx, r0, nr); },
+        [&](int r0, int nr) { mv_cols(st, nx, nr, w + r0, [&](int j, double a) { tq[nu + j] += a; }); });
+    // rbar2 = (L^R_k)^{-1} rhat
+    for_blocks(
+        st, nu, nu, [&](int r0, int nr) { stage_tri(st, blk, nu, r0, nr); },
+        [&](int r0, int nr) {
+          if (nr == nu) tri_solve<false>(st, nu, dr, tq, yb);
+        });
+    if (block_rows(st, nu) < nu && tid == 0) {
+      for (int i = 0; i < nu; ++i) {
+        double a = tq[i];
+        for (int j = 0; j < i; ++j) a -= fv.LR(k, i, j) * yb[j];
+        yb[i] = a * dr[i];
       }
-      __syncthreads();
-      for (int i = tid; i < nx; i += nt) {
-        double s = pn[i];
-        for (int j = 0; j <= i; ++j) s += fv.LQ(k + 1, i, j) * t1[j];
-        w[i] = s;
-      }
-      __syncthreads();
-      for (int i = tid; i < nux; i += nt) {
-        double s;
-        if (i < nu) {
-          s = -ru[i];
-          for (int m = 0; m < nx; ++m) s += Bk[m * nu + i] * w[m];
-        } else {
-          s = k > 0 ? -rx[i - nu] : 0.0;
-          for (int m = 0; m < nx; ++m) s += Ak[m * nx + (i - nu)] * w[m];
-        }
-        tq[i] = s;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        for (int i = 0; i < nu; ++i) {
-          double s = tq[i];
-          for (int j = 0; j < i; ++j) s -= fv.LR(k, i, j) * tq[j];
-          tq[i] = s * fv.dR(k, i);
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < nu; i += nt) rbar2[(int64_t)k * nu + i] = tq[i];
-      if (k > 0)
-        for (int i = tid; i < nx; i += nt) {
-          double s = tq[nu + i];
-          for (int j = 0; j < nu; ++j) s -= fv.LS(k, i, j) * tq[j];
-          pn[i] = s;
-          p2[(int64_t)k * nx + i] = s;
-        }
     }
     __syncthreads();
+    for (int j = tid; j < nu; j += nt) rbar2[(int64_t)k * nu + j] = yb[j];
+    // p2_k = qhat - L^S_k rbar2
+    if (k > 0) {
+      for_blocks(
+          st, nx, nu, [&](int r0, int nr) { stage_dense(st, blk + off_LS(nx, nu), nu, r0, nr); },
+          [&](int r0, int nr) {
+            mv_rows(st, nu, nr, yb, [&](int i, double a) {
+              const double pk = tq[nu + r0 + i] - a;
+              pn[r0 + i] = pk;
+              p2[(int64_t)k * nx + r0 + i] = pk;
+            });
+          });
+    }
   }
 }
 
@@ -614,7 +844,10 @@ __device__ void solve_one(const SolveArgs& a, int b, double* sm, double* red) {
   double* flam = p2 + (int64_t)(N + 1) * nx;
   // with checkpoints the factor-sweep scratch comes first in LDS, the solve vectors after it
   double* fsm = sm;
-  double* ssm = sc ? sm + a.lds_factor_doubles : sm;
+  Stage st;
+  st.buf = sc ? sm + a.lds_factor_doubles : sm;
+  st.cap = a.stage_doubles;
+  double* ssm = st.buf + st.cap;
   __shared__ int s_bad, s_info;
   TF* seg = (TF*)a.F + D.oF + (sc ? ckpt_slots(N, sc) * fv.fs : 0);
   auto recompute = [&](int k0, int k1) {  // factors of stages [k0, k1) into the segment buffer
@@ -628,26 +861,26 @@ __device__ void solve_one(const SolveArgs& a, int b, double* sm, double* red) {
   auto forward = [&](const double* rb, const double* pv, const double* fl, int mode) {
     fwd_init(v, mode, ssm);
     if (!sc) {
-      fwd_sweep<TF>(v, fv, rb, pv, fl, mode, ssm, 0, N);
+      fwd_sweep<TF>(v, fv, rb, pv, fl, mode, ssm, st, 0, N);
       return;
     }
     for (int k0 = 0; k0 < N; k0 += sc) {
       const int k1 = k0 + sc < N ? k0 + sc : N;
       recompute(k0, k1);
-      fwd_sweep<TF>(v, fv, rb, pv, fl, mode, ssm, k0, k1);
+      fwd_sweep<TF>(v, fv, rb, pv, fl, mode, ssm, st, k0, k1);
     }
   };
   // residual (+ correction sweep) pass, backward over all stages
   auto residual = [&](bool sweep) -> double {
     double mr, mb;
-    resid_init(v, sweep, p2, ssm, mr, mb);
+    resid_init(v, sweep, p2, ssm, st, mr, mb);
     if (!sc) {
-      resid_bwd<TF>(v, fv, sweep, rb2, p2, flam, ssm, mr, mb, 0, N);
+      resid_bwd<TF>(v, fv, sweep, rb2, p2, flam, ssm, st, mr, mb, 0, N);
     } else {
       for (int k1 = N; k1 > 0;) {
         const int k0 = ((k1 - 1) / sc) * sc;
         if (sweep) recompute(k0, k1);
-        resid_bwd<TF>(v, fv, sweep, rb2, p2, flam, ssm, mr, mb, k0, k1);
+        resid_bwd<TF>(v, fv, sweep, rb2, p2, flam, ssm, st, mr, mb, k0, k1);
         k1 = k0;
       }
     }
@@ -781,7 +1014,14 @@ size_t generic_factor_lds(int nx, int nu) {
   const int nux = nx + nu;
   return sizeof(double) * ((size_t)nux * nux + (size_t)nx * nx + (size_t)nux * nx + 3 * nx + 2 * nux);
 }
-size_t generic_solve_lds(int nx, int nu) { return sizeof(double) * (size_t)(8 * nx + 4 * nu); }
+// LDS of the solve: the staging buffer (the largest stage matrix, at most 12288 doubles; larger
+// ones go through in row blocks) and the sweep vectors.
+size_t generic_stage_doubles(int nx, int nu) {
+  const size_t m = nx > nu ? nx : nu;
+  const size_t full = m * (m + 1);
+  return full < 12288 ? full : (12288 > m + 1 ? 12288 : m + 1);
+}
+size_t generic_solve_lds(int nx, int nu) { return sizeof(double) * (size_t)(9 * nx + 6 * nu); }
 
 template <int NT>
 static hipError_t factor_nt(lq_mode mode, const Desc* desc, int batch, const lq_data& d, void* F, double* V,
@@ -804,6 +1044,7 @@ hipError_t launch_factor_generic(lq_mode mode, const Desc* desc, int batch, cons
   switch (c.threads) {
     case 64: return factor_nt<64>(mode, desc, batch, d, F, V, info, lds, c, st);
     case 256: return factor_nt<256>(mode, desc, batch, d, F, V, info, lds, c, st);
+    case 512: return factor_nt<512>(mode, desc, batch, d, F, V, info, lds, c, st);
     default: return factor_nt<128>(mode, desc, batch, d, F, V, info, lds, c, st);
   }
 }
@@ -826,47 +1067,47 @@ hipError_t launch_solve_generic(lq_mode mode, const SolveArgs& a, size_t lds, co
   switch (c.threads) {
     case 64: return solve_nt<64>(mode, a, lds, c, st);
     case 256: return solve_nt<256>(mode, a, lds, c, st);
+    case 512: return solve_nt<512>(mode, a, lds, c, st);
     default: return solve_nt<128>(mode, a, lds, c, st);
   }
 }
 
 // Raise the dynamic-LDS limit of every generic factor instantiation (done once per plan, not
 // inside calls, so the calls stay capturable in a graph).
-hipError_t prepare_generic(size_t lds_factor) {
-  hipError_t e = hipSuccess;
-  const void* ks[] = {(const void*)k_factor_generic<64, double, double>, (const void*)k_factor_generic<128, double, double>,
-                      (const void*)k_factor_generic<256, double, double>, (const void*)k_factor_generic<64, float, float>,
-                      (const void*)k_factor_generic<128, float, float>, (const void*)k_factor_generic<256, float, float>,
-                      (const void*)k_solve_generic<64, double>, (const void*)k_solve_generic<128, double>,
-                      (const void*)k_solve_generic<256, double>, (const void*)k_solve_generic<64, float>,
-                      (const void*)k_solve_generic<128, float>, (const void*)k_solve_generic<256, float>};
-  for (const void* k : ks) {
-    hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_factor);
-    if (r != hipSuccess) e = r;
+template <int NT>
+static const void* generic_kernel(bool factor, lq_mode mode) {
+  if (factor)
+    return mode == LQ_F64 ? (const void*)k_factor_generic<NT, double, double> : (const void*)k_factor_generic<NT, float, float>;
+  return mode == LQ_F64 ? (const void*)k_solve_generic<NT, double> : (const void*)k_solve_generic<NT, float>;
+}
+
+static const void* generic_kernel(int threads, bool factor, lq_mode mode) {
+  switch (threads) {
+    case 64: return generic_kernel<64>(factor, mode);
+    case 256: return generic_kernel<256>(factor, mode);
+    case 512: return generic_kernel<512>(factor, mode);
+    default: return generic_kernel<128>(factor, mode);
   }
+}
+
+// Raise the dynamic-LDS limit of the generic factor (factor = true) or solve instantiations (done
+// once per plan, not inside calls, so the calls stay capturable in a graph).
+hipError_t prepare_generic(bool factor, size_t lds) {
+  hipError_t e = hipSuccess;
+  for (int t : {64, 128, 256, 512})
+    for (lq_mode m : {LQ_F64, LQ_MIXED_F32}) {
+      hipError_t r =
+          hipFuncSetAttribute(generic_kernel(t, factor, m), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (r != hipSuccess) e = r;
+    }
   return e;
 }
 
 // Workgroups of the generic kernels that fit on one CU at the given LDS size.
 int generic_blocks_per_cu(int threads, size_t lds, bool factor, lq_mode mode) {
   int n = 0;
-  const void* k = nullptr;
-  if (factor) {
-    k = mode == LQ_F64 ? (threads == 64 ? (const void*)k_factor_generic<64, double, double>
-                         : threads == 256 ? (const void*)k_factor_generic<256, double, double>
-                                          : (const void*)k_factor_generic<128, double, double>)
-                       : (threads == 64 ? (const void*)k_factor_generic<64, float, float>
-                         : threads == 256 ? (const void*)k_factor_generic<256, float, float>
-                                          : (const void*)k_factor_generic<128, float, float>);
-  } else {
-    k = mode == LQ_F64 ? (threads == 64 ? (const void*)k_solve_generic<64, double>
-                         : threads == 256 ? (const void*)k_solve_generic<256, double>
-                                          : (const void*)k_solve_generic<128, double>)
-                       : (threads == 64 ? (const void*)k_solve_generic<64, float>
-                         : threads == 256 ? (const void*)k_solve_generic<256, float>
-                                          : (const void*)k_solve_generic<128, float>);
-  }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, generic_kernel(threads, factor, mode), threads, lds) !=
+      hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }

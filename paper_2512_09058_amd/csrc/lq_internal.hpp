@@ -105,6 +105,7 @@ struct SolveArgs {
   int32_t* info;
   int32_t ckpt;                // checkpoint stride of the factors (0: every stage stored)
   int32_t lds_factor_doubles;  // with checkpoints: LDS doubles of the factor scratch
+  int32_t stage_doubles;       // LDS doubles of the stage-matrix staging buffer
 };
 
 // Launch shape of the generic kernels: threads per workgroup (64, 128 or 256); without a

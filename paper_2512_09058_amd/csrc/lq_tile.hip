@@ -26,9 +26,10 @@
 // of the next stage.  The right-hand-side sweep (rbar_k, p_k) runs in float64 beside it, as in
 // the other factor kernels, and the factor blocks use the shared workspace layout.
 //
-// Precision: TP is the type of the stage products (float64, or float32 in the mixed mode, whose
-// operands are the float32-rounded L^Q and C); the potrf and everything after it is float64 and
-// the factors are rounded to TF for storage.
+// Precision: TP is the type of the stage products: float64; float32 (mixed mode: operands the
+// float32-rounded L^Q and C, float32 accumulation); or bf16 operands with float32 accumulation
+// (rounded from the float32 L^Q, C and W).  The potrf and everything after it is float64 and the
+// factors are rounded to TF for storage.
 #include <math.h>
 
 #include <type_traits>
@@ -88,6 +89,27 @@ struct MM<float> {
   }
 };
 
+// bf16 operands with float32 accumulation: one 16x16x16 instruction per tile product.  Operand
+// slot i of lane 16 g + c holds contraction index 4 g + i, so a float32 fragment (row 4g + t in
+// slot t) is directly the B operand and the A operand is four consecutive entries of a row.
+struct BF16 {};
+typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+template <>
+struct MM<BF16> {
+  typedef f4 V;
+  static __device__ __forceinline__ int row(int t, int g) { return 4 * g + t; }
+};
+
+// Element type of W slabs and of converted C fragments for a product type.
+template <typename TP>
+struct Elem {
+  typedef TP type;
+};
+template <>
+struct Elem<BF16> {
+  typedef float type;
+};
+
 // Leading dimensions of LDS tiles (padded against bank conflicts; float rows stay 16-byte aligned).
 template <typename T>
 struct Ld;
@@ -105,14 +127,25 @@ struct Ld<float> {
 template <typename TP, bool TR, bool NEG = false, typename TM>
 __device__ __forceinline__ typename MM<TP>::V tmm(typename MM<TP>::V acc, const TM* M, int ld,
                                                    const typename MM<TP>::V& X, int g, int c) {
+  if constexpr (std::is_same<TP, BF16>::value) {
+    b4 av, bv;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int kk = MM<TP>::row(s, g);
-    TP av = (TP)(TR ? M[kk * ld + c] : M[c * ld + kk]);
-    if (NEG) av = -av;
-    acc = MM<TP>::mma(av, X[s], acc);
+    for (int i = 0; i < 4; ++i) {
+      const float m = (float)(TR ? M[(4 * g + i) * ld + c] : M[c * ld + 4 * g + i]);
+      av[i] = (__bf16)(NEG ? -m : m);
+      bv[i] = (__bf16)X[i];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = MM<TP>::row(s, g);
+      TP av = (TP)(TR ? M[kk * ld + c] : M[c * ld + kk]);
+      if (NEG) av = -av;
+      acc = MM<TP>::mma(av, X[s], acc);
+    }
+    return acc;
   }
-  return acc;
 }
 
 // Right-looking Cholesky of a 16x16 tile held one row per lane (lane c of each 16-lane row:
@@ -182,7 +215,8 @@ __device__ __forceinline__ void factor_tile_one(const Desc& D, const lq_data& d,
                                 unsigned char* lds, int& s_info) {
   constexpr bool F64 = std::is_same<TP, double>::value;
   typedef typename MM<TP>::V PV;
-  constexpr int LQ = Ld<TF>::v, LW = Ld<TP>::v, LD = Ld<double>::v;
+  typedef typename Elem<TP>::type TE;  // W slabs, converted C fragments
+  constexpr int LQ = Ld<TF>::v, LW = Ld<TE>::v, LD = Ld<double>::v;
   const int N = D.N, nx = D.nx, nu = D.nu;
   const int TU = (nu + 15) >> 4, TX = (nx + 15) >> 4, T = TU + TX;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -193,7 +227,7 @@ __device__ __forceinline__ void factor_tile_one(const Desc& D, const lq_data& d,
   TF* LQB = (TF*)(lds + L.oLQB);
   double* UP = (double*)(lds + L.oUP);
   double* XP = (double*)(lds + L.oXP);
-  TP* WS = (TP*)(lds + L.oWS);
+  TE* WS = (TE*)(lds + L.oWS);
   double* DI = (double*)(lds + L.oDI);
   double* SC = (double*)(lds + L.oSC);
   // per-wavefront relayout tile of the mixed mode, in the slab region (dead at that point)
@@ -353,12 +387,12 @@ __device__ __forceinline__ void factor_tile_one(const Desc& D, const lq_data& d,
             }
             PV cx;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) cx[t] = (TP)cur[t];
+            for (int t = 0; t < 4; ++t) cx[t] = (TE)cur[t];
             Wf = tmm<TP, false>(Wf, lqb(m, mp), LQ, cx, g, c);
             cur = nxt;
             nxt = nn;
           }
-          TP* ws = wsl(m, a);
+          TE* ws = wsl(m, a);
 #pragma unroll
           for (int t = 0; t < 4; ++t) ws[MM<TP>::row(t, g) * LW + c] = Wf[t];
         }
@@ -552,7 +586,23 @@ __global__ void k_reset_counter_tile(int32_t* c) {
 template <int TMAX>
 const void* tile_kernel(lq_mode mode) {
   if (mode == LQ_F64) return (const void*)k_factor_tile<TMAX, double, double>;
+  if (mode == LQ_MIXED_BF16) return (const void*)k_factor_tile<TMAX, float, BF16>;
   return (const void*)k_factor_tile<TMAX, float, float>;
+}
+
+template <int TMAX>
+hipError_t launch_tile(lq_mode mode, dim3 grid, dim3 block, size_t lds, hipStream_t st, const Desc* desc, int batch,
+                       const lq_data& d, void* F, double* V, int32_t* info, const GenericLaunch& c) {
+  if (mode == LQ_F64)
+    hipLaunchKernelGGL((k_factor_tile<TMAX, double, double>), grid, block, lds, st, desc, batch, d, (double*)F, V,
+                       info, c.order, c.counter);
+  else if (mode == LQ_MIXED_BF16)
+    hipLaunchKernelGGL((k_factor_tile<TMAX, float, BF16>), grid, block, lds, st, desc, batch, d, (float*)F, V, info,
+                       c.order, c.counter);
+  else
+    hipLaunchKernelGGL((k_factor_tile<TMAX, float, float>), grid, block, lds, st, desc, batch, d, (float*)F, V,
+                       info, c.order, c.counter);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -563,7 +613,7 @@ int tile_max_columns() { return 10; }
 // Wavefronts per workgroup (= instantiated column count) for an instance set of at most T columns.
 int tile_waves(int T) { return T <= 5 ? 5 : 10; }
 
-bool tile_mode_supported(lq_mode mode) { return mode == LQ_F64 || mode == LQ_MIXED_F32; }
+bool tile_mode_supported(lq_mode mode) { return mode == LQ_F64 || mode == LQ_MIXED_F32 || mode == LQ_MIXED_BF16; }
 
 size_t tile_lds_bytes(int nx, int nu, lq_mode mode) {
   const TileLds L = tile_lds((nu + 15) / 16, (nx + 15) / 16, mode == LQ_F64);
@@ -589,22 +639,8 @@ hipError_t launch_factor_tile(lq_mode mode, int waves, const Desc* desc, int bat
                               double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st) {
   if (c.counter) hipLaunchKernelGGL(k_reset_counter_tile, dim3(1), dim3(64), 0, st, c.counter);
   const dim3 grid(c.counter ? c.grid : batch), block(64 * waves);
-  if (waves == 5) {
-    if (mode == LQ_F64)
-      hipLaunchKernelGGL((k_factor_tile<5, double, double>), grid, block, lds, st, desc, batch, d, (double*)F, V,
-                         info, c.order, c.counter);
-    else
-      hipLaunchKernelGGL((k_factor_tile<5, float, float>), grid, block, lds, st, desc, batch, d, (float*)F, V,
-                         info, c.order, c.counter);
-  } else {
-    if (mode == LQ_F64)
-      hipLaunchKernelGGL((k_factor_tile<10, double, double>), grid, block, lds, st, desc, batch, d, (double*)F, V,
-                         info, c.order, c.counter);
-    else
-      hipLaunchKernelGGL((k_factor_tile<10, float, float>), grid, block, lds, st, desc, batch, d, (float*)F, V,
-                         info, c.order, c.counter);
-  }
-  return hipGetLastError();
+  if (waves == 5) return launch_tile<5>(mode, grid, block, lds, st, desc, batch, d, F, V, info, c);
+  return launch_tile<10>(mode, grid, block, lds, st, desc, batch, d, F, V, info, c);
 }
 
 }  // namespace lq

@@ -20,7 +20,7 @@ import torch
 from . import api
 
 PERSISTENCE = ((0, 0), (1, 0), (1, 1), (1, 2))
-CANDIDATES = [{"threads": t, "persistent": p, "blocks_per_cu": b} for t in (64, 128, 256) for p, b in PERSISTENCE]
+CANDIDATES = [{"threads": t, "persistent": p, "blocks_per_cu": b} for t in (64, 128, 256, 512) for p, b in PERSISTENCE]
 
 
 def candidates(plan: api.Plan):

@@ -53,7 +53,7 @@ def _well_conditioned(seed, N, nx, nu):
 
 
 @pytest.mark.parametrize("N,nx,nu", SHAPES)
-@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 8)])
+@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 8), ("mixed_bf16", 40)])
 def test_tile_matches_oracle(N, nx, nu, mode, max_it):
     print(f"case: tile N={N} nx={nx} nu={nu} {mode}", flush=True)
     insts = [_well_conditioned(300 + i, N, nx, nu) for i in range(3)]
@@ -159,7 +159,20 @@ def test_large_workload_full_size_sampled():
     inst = [synth.make_instance(4, i) for i in range(4)]
     insts = [inst[i % 4] for i in range(64)]
     print("case: workload 4 full size, tile", flush=True)
-    for mode, mi in (("f64", 0), ("mixed_f32", 8)):
+    for mode, mi in (("f64", 0), ("mixed_f32", 8), ("mixed_bf16", 30)):
         res = run(insts, mode, max_it=mi)
         assert res["plan"].variant == "tile"
         _check(res, sample=[0, 1, 63])
+
+
+def test_bf16_plans_only_where_the_tile_kernel_runs():
+    """The bf16 mode exists only on the matrix-core tile kernel: checkpointed plans and shapes it
+    does not take are refused instead of silently running float32 products."""
+    with pytest.raises(RuntimeError, match="status -2"):
+        L.Plan(20, 12, 4, batch=2, mode="mixed_bf16", ckpt_stride=5)
+    with pytest.raises(RuntimeError, match="status -2"):
+        L.Plan(20, 170, 4, batch=2, mode="mixed_bf16")
+    plan = L.Plan(20, 12, 4, batch=2, mode="mixed_bf16")
+    assert plan.variant == "tile"
+    with pytest.raises(RuntimeError, match="status -2"):
+        plan.set_variant("generic")

@@ -442,6 +442,11 @@ __device__ __forceinline__ void factor_tile_one(const Desc& D, const lq_data& d,
     const int j0 = k == N ? TU : 0, j1 = k == 0 ? TU : T;
     for (int j = j0; j < j1; ++j) {
       if (own && a == j) {
+        // lane coordinates re-derived here so that the diagonal step's per-lane addresses and
+        // masks are not kept live across the whole pivot loop
+        int dt = tid;
+        asm volatile("" : "+v"(dt));
+        const int lane = dt & 63, g = lane >> 4, c = lane & 15;
         d4 Gj = G[0];
 #pragma unroll
         for (int bb = 1; bb < TMAX; ++bb)
@@ -564,8 +569,16 @@ __device__ __forceinline__ void factor_tile_one(const Desc& D, const lq_data& d,
   }
 }
 
+// Wavefronts per SIMD the register allocation targets: enough resident workgroups that several
+// instances share a CU (their latency chains overlap).
+template <int TMAX>
+struct TileOcc {
+  static constexpr int v = 3;
+};
+
 template <int TMAX, typename TF, typename TP>
-__global__ void __launch_bounds__(64 * TMAX) k_factor_tile(const Desc* __restrict__ desc, int batch, lq_data d,
+__global__ void __launch_bounds__(64 * TMAX) __attribute__((amdgpu_waves_per_eu(TileOcc<TMAX>::v)))
+k_factor_tile(const Desc* __restrict__ desc, int batch, lq_data d,
                                                           TF* __restrict__ F, double* __restrict__ Vws,
                                                           int32_t* __restrict__ info, const int32_t* __restrict__ order,
                                                           int32_t* counter) {
@@ -611,7 +624,7 @@ hipError_t launch_tile(lq_mode mode, dim3 grid, dim3 block, size_t lds, hipStrea
 int tile_max_columns() { return 10; }
 
 // Wavefronts per workgroup (= instantiated column count) for an instance set of at most T columns.
-int tile_waves(int T) { return T <= 5 ? 5 : 10; }
+int tile_waves(int T) { return T <= 3 ? 3 : T <= 5 ? 5 : 10; }
 
 bool tile_mode_supported(lq_mode mode) { return mode == LQ_F64 || mode == LQ_MIXED_F32 || mode == LQ_MIXED_BF16; }
 
@@ -621,13 +634,13 @@ size_t tile_lds_bytes(int nx, int nu, lq_mode mode) {
 }
 
 hipError_t prepare_tile(int waves, lq_mode mode, size_t lds) {
-  const void* k = waves == 5 ? tile_kernel<5>(mode) : tile_kernel<10>(mode);
+  const void* k = waves == 3 ? tile_kernel<3>(mode) : waves == 5 ? tile_kernel<5>(mode) : tile_kernel<10>(mode);
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 int tile_blocks_per_cu(int waves, lq_mode mode, size_t lds) {
   int n = 0;
-  const void* k = waves == 5 ? tile_kernel<5>(mode) : tile_kernel<10>(mode);
+  const void* k = waves == 3 ? tile_kernel<3>(mode) : waves == 5 ? tile_kernel<5>(mode) : tile_kernel<10>(mode);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * waves, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
@@ -639,6 +652,7 @@ hipError_t launch_factor_tile(lq_mode mode, int waves, const Desc* desc, int bat
                               double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st) {
   if (c.counter) hipLaunchKernelGGL(k_reset_counter_tile, dim3(1), dim3(64), 0, st, c.counter);
   const dim3 grid(c.counter ? c.grid : batch), block(64 * waves);
+  if (waves == 3) return launch_tile<3>(mode, grid, block, lds, st, desc, batch, d, F, V, info, c);
   if (waves == 5) return launch_tile<5>(mode, grid, block, lds, st, desc, batch, d, F, V, info, c);
   return launch_tile<10>(mode, grid, block, lds, st, desc, batch, d, F, V, info, c);
 }

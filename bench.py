@@ -182,12 +182,224 @@ def bench_uneven(args):
         relh = rel.cpu().numpy()
         worst = max(kkt.residual(insts[i], L.unpack(plan, "x", x, i), L.unpack(plan, "u", u, i),
                                  L.unpack(plan, "lam", lam, i))[1] for i in (0, 1023, 2047))
-        out[mode] = {"value": 2048 / (ms * 1e-3), "ms_per_step": ms, "launch": choice["launch"],
+        out[mode] = {"value": 2048 / (ms * 1e-3), "ms_per_step": ms, "variant": choice["variant"],
+                     "launch": choice["launch"],
                      "max_rel_res": float(relh.max()), "iters_max": int(its.max().item()),
                      "info_ok": bool((info == 0).all().item()), "oracle_rel_res_sampled": worst}
-        print(f"[bench] uneven {mode}: {ms:.2f} ms/step, launch {choice['launch']}, max rel_res {relh.max():.2e}",
+        print(f"[bench] uneven {mode}: {ms:.2f} ms/step, variant {choice['variant']}, launch {choice['launch']}, "
+              f"max rel_res {relh.max():.2e}",
               file=sys.stderr, flush=True)
     out["value"] = out["mixed_f32"]["value"]
+    print(json.dumps(out))
+
+
+def _gen_worker(args):
+    import synth
+    cfg, i = args
+    p = synth.make_instance(cfg, i)
+    return i, {k: getattr(p, k) for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+
+
+def _gen_uniform(cfg, count, workers=16):
+    """`count` instances of workload `cfg`, generated in parallel processes, as the packed device
+    arrays of the library (uniform batch: instance blocks back to back)."""
+    import torch
+    import synth
+    print(f"[bench] generating {count} instances in {min(workers, count)} processes", file=sys.stderr, flush=True)
+    first = synth.make_instance(cfg, 0)
+    host = {k: np.empty((count,) + getattr(first, k).shape) for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"  # one BLAS thread per worker process
+    ctx = mp.get_context("spawn")
+    done = 0
+    with ctx.Pool(min(workers, count)) as pool:
+        for i, d in pool.imap_unordered(_gen_worker, [(cfg, i) for i in range(count)]):
+            for k, v in d.items():
+                host[k][i] = v
+            done += 1
+            if done % 8 == 0:
+                print(f"[bench] generated {done}/{count} instances", file=sys.stderr, flush=True)
+    return {k: torch.from_numpy(v.reshape(-1)).to("cuda") for k, v in host.items()}
+
+
+def _oracle_time_worker(args):
+    import synth
+    from oracle import adjoint, kkt, riccati
+    cfg, start, count, adj = args
+    probs = [synth.make_instance(cfg, i) for i in range(start, start + count)]
+    t0 = time.perf_counter()
+    for p in probs:
+        if adj:
+            x, u, _ = kkt.solve_dense(p)
+            _, gx, gu = adjoint.quad_loss(x, u)
+            adjoint.adjoint_grad(p, gx, gu)
+        else:
+            riccati.solve(p)
+    return time.perf_counter() - t0
+
+
+def _cpu_uniform(cfg, per, workers, adj, what):
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        times = pool.map(_oracle_time_worker, [(cfg, w * per, per, adj) for w in range(workers)])
+    n, t = per * workers, max(times)
+    return {"value": n / t, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n} instances of the workload, {what} (numpy float64, 1 BLAS thread per process), "
+                      f"{workers} processes, slowest {t:.1f} s"}
+
+
+def _roofline(ms, nbytes, flops, peak_flops_tf):
+    """Roofline entry of one launch: HBM-bound if its arithmetic intensity (algorithmic flops per
+    algorithmic byte) is below the ridge point of the given matrix-core peak, else compute-bound."""
+    ai = flops / nbytes
+    if ai < peak_flops_tf * 1e12 / (HBM_PEAK_GBS * 1e9):
+        a = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+                "traffic": None, "algorithmic_bytes_per_launch": nbytes, "ms_per_launch": ms}
+    a = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": a, "peak": peak_flops_tf, "unit": "TFLOP/s", "frac": a / peak_flops_tf,
+            "traffic": None, "algorithmic_flops_per_launch": flops, "ms_per_launch": ms}
+
+
+def factor_flops(batch, N, nx, nu):
+    """Operation count of the factor sweep (FMA = 2 flops): trmm 1/2 nux nx^2 + syrk 1/2 nux^2 nx +
+    potrf nux^3/6 per stage."""
+    ux = nx + nu
+    return 2.0 * batch * N * (0.5 * ux * nx * nx + 0.5 * ux * ux * nx + ux ** 3 / 6.0)
+
+
+def bench_large(args):
+    """The large workload: 64 instances, N = 1000, nx = 128, nu = 32 (A = 0.99 Haar + 0.01 G,
+    B = G / sqrt(nx), Q = M M^T + I, R = I); bf16 matrix-core stage products with float64
+    Cholesky and refinement (the reported path), float32 products and plain float64 beside it."""
+    import torch
+    import paper_2512_09058_amd as L
+    from oracle import riccati
+    b, Nn, nx, nu = 64, 1000, 128, 32
+    t0 = time.perf_counter()
+    data = _gen_uniform(4, b)
+    torch.cuda.synchronize()
+    print(f"[bench] generated and uploaded the large workload in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    res = {}
+    for mode, mi in (("f64", 0), ("mixed_f32", args.max_it), ("mixed_bf16", max(args.max_it, 20))):
+        plan = L.Plan(Nn, nx, nu, batch=b, mode=mode)
+        plan.set_launch(threads=512)
+        ws = plan.workspace()
+        info = torch.zeros(b, dtype=torch.int32, device="cuda")
+        rel = torch.zeros(b, dtype=torch.float64, device="cuda")
+        its = torch.zeros(b, dtype=torch.int32, device="cuda")
+        x, u, lam = plan.empty_outputs()
+        stream = torch.cuda.current_stream()
+        ev = []
+        for s_ in range(args.warmup + args.steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            L.factor(plan, data, ws, info, stream=stream)
+            e[1].record(stream)
+            L.solve(plan, data, ws, x, u, lam, rel, its, info, tol=TOL, max_it=mi, check_res=True, stream=stream)
+            e[2].record(stream)
+            if s_ >= args.warmup:
+                ev.append(e)
+        torch.cuda.synchronize()
+        tf = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        tsv = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        relh = rel.cpu().numpy()
+        r = {"value": b / ((tf + tsv) * 1e-3), "ms_per_step": tf + tsv, "ms_factor": tf, "ms_solve": tsv,
+             "max_rel_res": float(relh.max()), "iters_max": int(its.max().item()),
+             "info_ok": bool((info == 0).all().item()), "variant": plan.variant}
+        sol = [L.unpack(plan, n, t, 0) for n, t in (("x", x), ("u", u), ("lam", lam))]
+        ref = riccati.solve(synthetic_instance(4, 0))
+        r["forward_error_inst0"] = float(max(np.abs(a_ - b_).max() for a_, b_ in zip(sol, ref)) /
+                                         max(np.abs(b_).max() for b_ in ref))
+        fb = 8 if mode == "f64" else 4
+        r["factor_roofline"] = _roofline(tf, algorithmic_bytes_factor(b, Nn, nx, nu, fb), factor_flops(b, Nn, nx, nu),
+                                         78.6)
+        r["solve_GBps_algorithmic"] = algorithmic_bytes_solve(Nn, nx, nu, fb, its.cpu().numpy()) / (tsv * 1e-3) / 1e9
+        res[mode] = r
+        print(f"[bench] large {mode}: factor {tf:.1f} ms, solve {tsv:.1f} ms, max rel_res {relh.max():.2e}, "
+              f"iterations {r['iters_max']}", file=sys.stderr, flush=True)
+    m = res["mixed_bf16"]
+    dom_solve = m["ms_solve"] >= m["ms_factor"]
+    out = {"metric": "LQ KKT solves/s, batch 64 nx=128 nu=32 N=1000: bf16 products + f64 refinement vs FP64",
+           "value": m["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 stage products (f32 accumulate) + f64 Cholesky/residual/refinement",
+           "data": "synthetic (seeded generators of the workload)",
+           "config": {"workload": "batch 64 LQ problems, N=1000, nx=128, nu=32", "batch": b, "N": Nn, "nx": nx,
+                      "nu": nu, "tol": TOL},
+           "paths": res,
+           "roofline": (m["factor_roofline"] if not dom_solve else
+                        {"bound": "hbm", "kernel": "solve", "achieved": m["solve_GBps_algorithmic"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": m["solve_GBps_algorithmic"] / HBM_PEAK_GBS,
+                         "traffic": None, "ms_per_launch": m["ms_solve"]}),
+           "cpu_baseline": None if args.no_cpu else _cpu_uniform(4, 1, 8, False, "textbook Riccati route")}
+    print(json.dumps(out))
+
+
+def synthetic_instance(cfg, i):
+    import synth
+    return synth.make_instance(cfg, i)
+
+
+def bench_adjoint(args):
+    """The adjoint workload: 1024 instances, N = 100, nx = 32, nu = 8 (generators of the batch-4096
+    workload); one step = factor + solve + lq_solve_backward for the loss 1/2 sum(|x_k|^2 + |u_k|^2)
+    (upstream gradients x, u), float32 products with float64 Cholesky and refinement, factors
+    checkpointed every 10 stages (the reported path); without checkpoints and in float64 beside it."""
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    b = 1024
+    prob = synth.make_batch(5)
+    data = L.pack(prob)
+    Nn, nx, nu = prob.N, prob.nx, prob.nu
+    res = {}
+    for mode, ckpt, mi in (("mixed_f32", 10, args.max_it), ("mixed_f32", 0, args.max_it), ("f64", 0, 0)):
+        plan = L.Plan(Nn, nx, nu, batch=b, mode=mode, ckpt_stride=ckpt)
+        ws = plan.workspace()
+        info = torch.zeros(b, dtype=torch.int32, device="cuda")
+        rel = torch.zeros(b, dtype=torch.float64, device="cuda")
+        relb = torch.zeros(b, dtype=torch.float64, device="cuda")
+        x, u, lam = plan.empty_outputs()
+        g = {k: torch.empty(plan.totals[k], dtype=torch.float64, device="cuda")
+             for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+        stream = torch.cuda.current_stream()
+        ev = []
+        for s_ in range(args.warmup + args.steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            L.factor(plan, data, ws, info, stream=stream)
+            e[1].record(stream)
+            L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=mi, check_res=True, stream=stream)
+            e[2].record(stream)
+            L.solve_backward(plan, data, ws, x, u, lam, x, u, g, relb, None, info, tol=TOL, max_it=mi,
+                             stream=stream)
+            e[3].record(stream)
+            if s_ >= args.warmup:
+                ev.append(e)
+        torch.cuda.synchronize()
+        t = [float(np.mean([e[i].elapsed_time(e[i + 1]) for e in ev])) for i in range(3)]
+        key = f"{mode}" + (f"_ckpt{ckpt}" if ckpt else "")
+        res[key] = {"value": b / (sum(t) * 1e-3), "ms_per_step": sum(t), "ms_factor": t[0], "ms_solve": t[1],
+                    "ms_backward": t[2], "max_rel_res": float(rel.max().item()),
+                    "max_rel_res_adjoint": float(relb.max().item()), "info_ok": bool((info == 0).all().item()),
+                    "variant": plan.variant, "workspace_bytes": plan.workspace_bytes}
+        print(f"[bench] adjoint {key}: factor {t[0]:.2f} ms, solve {t[1]:.2f} ms, backward {t[2]:.2f} ms, "
+              f"rel {rel.max().item():.1e} / {relb.max().item():.1e}", file=sys.stderr, flush=True)
+    m = res["mixed_f32_ckpt10"]
+    out = {"metric": "LQ KKT forward+adjoint solves/s, batch 1024 nx=32 nu=8 N=100, factors checkpointed every 10",
+           "value": m["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 stage products + f64 Cholesky/residual/refinement",
+           "data": "synthetic (seeded generators of the workload)",
+           "config": {"workload": "batch 1024 LQ problems, N=100, nx=32, nu=8, forward + adjoint", "batch": b,
+                      "N": Nn, "nx": nx, "nu": nu, "tol": TOL, "ckpt_stride": 10},
+           "paths": res, "roofline": None,
+           "cpu_baseline": None if args.no_cpu else _cpu_uniform(5, 1, 16, True,
+                                                                 "dense KKT solve + dense adjoint solve")}
     print(json.dumps(out))
 
 
@@ -199,11 +411,13 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-it", type=int, default=10)
-    ap.add_argument("--workload", choices=["batch4096", "uneven2048"], default="batch4096",
-                    help="uneven2048: measure the 2048-instance uneven workload instead (separate line)")
+    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024"], default="batch4096",
+                    help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
+                         "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (scale for HBM counters)")
     args = ap.parse_args()
+    print(f"[bench] workload {args.workload}", file=sys.stderr, flush=True)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the instances of the batch are "
               "independent, so more GPUs would each run this same kernel on their own share; no multi-GPU run "
@@ -211,6 +425,7 @@ def main():
         sys.exit(2)
 
     import torch
+    print("[bench] torch imported", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         n = 1 << 27  # float64 elements = 1 GiB
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -228,6 +443,10 @@ def main():
 
     if args.workload == "uneven2048":
         return bench_uneven(args)
+    if args.workload == "large64":
+        return bench_large(args)
+    if args.workload == "adjoint1024":
+        return bench_adjoint(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)

@@ -389,13 +389,62 @@ struct Walk {
   }
 };
 
-constexpr int kStageUnroll = 8;
+constexpr int kStageUnroll = 16;
 
-// rows [r0, r0 + nr) of a row-major matrix with m columns
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+
+// rows [r0, r0 + nr) of a row-major matrix with m columns.  A 16-byte aligned source is read in
+// 16-byte vectors, kStageUnroll of them in flight per thread before the first LDS store.
 template <typename T>
 __device__ void stage_dense(const Stage& s, const T* __restrict__ M, int m, int r0, int nr) {
   const int n = nr * m, ld = m + 1, nt = blockDim.x;
   const T* src = M + (int64_t)r0 * m;
+  if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    typedef typename Vec16<T>::v V;
+    constexpr int W = Vec16<T>::n;
+    const V* vs = reinterpret_cast<const V*>(src);
+    const int nv = n / W;  // whole vectors; the tail below
+    Walk wk(threadIdx.x * W, nt * W, m);
+    for (int base = threadIdx.x; base < nv; base += kStageUnroll * nt) {
+      V v[kStageUnroll];
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) {
+        const int e = base + u * nt;
+        v[u] = vs[e < nv ? e : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) {
+        if (base + u * nt < nv) {
+          int i = wk.i, j = wk.j;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            s.buf[i * ld + j] = (double)v[u][w];
+            if (++j == m) {
+              j = 0;
+              ++i;
+            }
+          }
+        }
+        wk.next();
+      }
+    }
+    for (int e = nv * W + threadIdx.x; e < n; e += nt) {
+      const int i = e / m;
+      s.buf[i * ld + (e - i * m)] = (double)src[e];
+    }
+    return;
+  }
   Walk wk(threadIdx.x, nt, m);
   for (int base = threadIdx.x; base < n; base += kStageUnroll * nt) {
     T v[kStageUnroll];

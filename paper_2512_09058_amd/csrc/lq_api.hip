@@ -38,6 +38,14 @@ hipError_t prepare_tile(int waves, lq_mode mode, size_t lds);
 int tile_blocks_per_cu(int waves, lq_mode mode, size_t lds);
 hipError_t launch_factor_tile(lq_mode mode, int waves, const Desc* desc, int batch, const lq_data& d, void* F,
                               double* V, int32_t* info, size_t lds, const GenericLaunch& c, hipStream_t st);
+
+// Register-streaming solve kernels for nx <= 128, nu <= 64 (lq_tsolve.hip).
+bool tsolve_sizes(int maxnx, int maxnu, int* NXP, int* NUP);
+size_t tsolve_lds_bytes(int NXP, int NUP);
+hipError_t prepare_tsolve(int NXP, int NUP, lq_mode mode);
+int tsolve_blocks_per_cu(int NXP, int NUP, lq_mode mode);
+hipError_t launch_solve_tsolve(int NXP, int NUP, lq_mode mode, const SolveArgs& a, const GenericLaunch& c,
+                               hipStream_t st);
 }  // namespace lq
 
 using lq::Desc;
@@ -79,6 +87,7 @@ struct lq_plan {
   bool can_small = false, can_tile = false, can_generic = false;
   int tile_waves = 0;       // wavefronts per workgroup of the tile factor kernel
   size_t lds_tile = 0;      // its dynamic LDS bytes
+  int ts_nxp = 0, ts_nup = 0;  // padded sizes of the tile plan's solve kernel (0: generic solve)
   int32_t* order_d = nullptr;  // device: instance indices longest first (inside the desc allocation)
   size_t offCtr = 0;           // workspace: work counters of the persistent kernels
   int cu_count = 0;
@@ -91,8 +100,13 @@ struct lq_plan {
 static void update_grids(lq_plan* p) {
   for (int f = 0; f < 2; ++f) {
     const size_t lds = f ? p->lds_factor : p->lds_solve;
-    int per = (f && p->variant == VAR_TILE) ? lq::tile_blocks_per_cu(p->tile_waves, p->mode, p->lds_tile)
-                                            : lq::generic_blocks_per_cu(p->launch.threads, lds, f != 0, p->mode);
+    int per;
+    if (p->variant == VAR_TILE)
+      per = f ? lq::tile_blocks_per_cu(p->tile_waves, p->mode, p->lds_tile)
+              : p->ts_nxp ? lq::tsolve_blocks_per_cu(p->ts_nxp, p->ts_nup, p->mode)
+                          : lq::generic_blocks_per_cu(p->launch.threads, lds, false, p->mode);
+    else
+      per = lq::generic_blocks_per_cu(p->launch.threads, lds, f != 0, p->mode);
     if (p->launch.blocks_per_cu > 0 && p->launch.blocks_per_cu < per) per = p->launch.blocks_per_cu;
     const int64_t g = (int64_t)p->cu_count * per;
     const int32_t grid = (int32_t)(g < p->batch ? g : p->batch);
@@ -251,6 +265,11 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   if (p->can_tile && lq::prepare_tile(p->tile_waves, mode, p->lds_tile) != hipSuccess) {
     (void)hipGetLastError();
     p->can_tile = false;
+  }
+  if (p->can_tile && lq::tsolve_sizes(p->maxnx, p->maxnu, &p->ts_nxp, &p->ts_nup) &&
+      lq::prepare_tsolve(p->ts_nxp, p->ts_nup, mode) != hipSuccess) {
+    (void)hipGetLastError();
+    p->ts_nxp = p->ts_nup = 0;
   }
   if ((p->variant == VAR_GENERIC && !p->can_generic) || (p->variant == VAR_TILE && !p->can_tile)) {
     hipFree(p->desc_d);
@@ -414,6 +433,8 @@ extern "C" int lq_solve(const lq_plan* p, const lq_data* d, void* ws, const lq_s
   hipError_t e;
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_solve_small(p->mode, p->N[0], p->nx[0], p->nu[0], a, st);
+  else if (p->variant == VAR_TILE && p->ts_nxp)
+    e = lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, generic_launch(p, ws, false), st);
   else
     e = lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
   return launch_status(e, "lq_solve");
@@ -440,7 +461,9 @@ extern "C" int lq_solve_backward(const lq_plan* p, const lq_data* d, void* ws, c
   a.gx = gx; a.gu = gu;
   a.rhs = lq::RHS_ADJOINT;
   a.rel_res = rel_res; a.iters = iters; a.info = info;
-  hipError_t e = lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
+  hipError_t e = (p->variant == VAR_TILE && p->ts_nxp)
+                     ? lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, generic_launch(p, ws, false), st)
+                     : lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
   if ((rc = launch_status(e, "lq_solve_backward"))) return rc;
   lq::GradArgs g;
   g.desc = p->desc_d; g.batch = p->batch; g.d = *d;

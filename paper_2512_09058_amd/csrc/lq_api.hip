@@ -46,6 +46,16 @@ hipError_t prepare_tsolve(int NXP, int NUP, lq_mode mode);
 int tsolve_blocks_per_cu(int NXP, int NUP, lq_mode mode);
 hipError_t launch_solve_tsolve(int NXP, int NUP, lq_mode mode, const SolveArgs& a, const GenericLaunch& c,
                                hipStream_t st);
+
+// Checkpointed solve kernels of tile plans, nx <= 64, nu <= 64 (lq_tckpt.hip).
+bool tckpt_sizes(int maxnx, int maxnu, int* NXP, int* NUP);
+bool tckpt_mode_supported(lq_mode mode);
+int tckpt_waves(int NXP, int NUP);
+size_t tckpt_lds_bytes(int NXP, int NUP, size_t tile_lds);
+hipError_t prepare_tckpt(int NXP, int NUP, lq_mode mode, size_t lds);
+int tckpt_blocks_per_cu(int NXP, int NUP, lq_mode mode, size_t lds);
+hipError_t launch_solve_tckpt(int NXP, int NUP, lq_mode mode, const SolveArgs& a, size_t lds,
+                              const GenericLaunch& c, hipStream_t st);
 }  // namespace lq
 
 using lq::Desc;
@@ -88,6 +98,7 @@ struct lq_plan {
   int tile_waves = 0;       // wavefronts per workgroup of the tile factor kernel
   size_t lds_tile = 0;      // its dynamic LDS bytes
   int ts_nxp = 0, ts_nup = 0;  // padded sizes of the tile plan's solve kernel (0: generic solve)
+  size_t lds_tckpt = 0;        // checkpointed tile plans: LDS of the solve kernel
   int32_t* order_d = nullptr;  // device: instance indices longest first (inside the desc allocation)
   size_t offCtr = 0;           // workspace: work counters of the persistent kernels
   int cu_count = 0;
@@ -103,6 +114,7 @@ static void update_grids(lq_plan* p) {
     int per;
     if (p->variant == VAR_TILE)
       per = f ? lq::tile_blocks_per_cu(p->tile_waves, p->mode, p->lds_tile)
+              : p->ckpt ? lq::tckpt_blocks_per_cu(p->ts_nxp, p->ts_nup, p->mode, p->lds_tckpt)
               : p->ts_nxp ? lq::tsolve_blocks_per_cu(p->ts_nxp, p->ts_nup, p->mode)
                           : lq::generic_blocks_per_cu(p->launch.threads, lds, false, p->mode);
     else
@@ -177,8 +189,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     D.oF = aF;
     if (ckpt_stride > 0) {
       // checkpoint slots (stages 0, s, 2s, ..., N) and one segment buffer of s stage blocks
-      const int64_t s = ckpt_stride, nck = n / s + 1 + (n % s ? 1 : 0);
-      aF += (nck + s) * lq::stage_factor_elems(nx[i], nu[i]);
+      aF += (lq::ckpt_slots(n, ckpt_stride) + ckpt_stride) * lq::stage_factor_elems(nx[i], nu[i]);
     } else {
       aF += (n + 1) * lq::stage_factor_elems(nx[i], nu[i]);
     }
@@ -199,13 +210,20 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   for (int i = 0; i < batch; ++i) maxT = std::max(maxT, (nx[i] + 15) / 16 + (nu[i] + 15) / 16);
   p->can_small = p->uniform && ckpt_stride == 0 && lq::small_variant_available(mode, nx[0], nu[0]);
   p->can_generic = ldsf <= kLdsLimit && p->lds_solve <= kLdsLimit && mode != LQ_MIXED_BF16;
-  if (ckpt_stride == 0 && lq::tile_mode_supported(mode) && maxT <= lq::tile_max_columns() && p->maxnu <= 64 &&
-      p->lds_solve <= kLdsLimit) {
-    p->tile_waves = lq::tile_waves(maxT);
+  if (lq::tile_mode_supported(mode) && maxT <= lq::tile_max_columns() && p->maxnu <= 64) {
     size_t lt = 0;
     for (int i = 0; i < batch; ++i) lt = std::max(lt, lq::tile_lds_bytes(nx[i], nu[i], mode));
     p->lds_tile = lt;
-    p->can_tile = lt <= kLdsLimit;
+    if (ckpt_stride == 0) {
+      p->tile_waves = lq::tile_waves(maxT);
+      p->can_tile = lt <= kLdsLimit && p->lds_solve <= kLdsLimit;
+    } else if (lq::tckpt_mode_supported(mode) && lq::tckpt_sizes(p->maxnx, p->maxnu, &p->ts_nxp, &p->ts_nup)) {
+      // the solve recomputes segments with the factor sweep: both kernels use the same wavefront
+      // count, so that the recomputed blocks are the factor kernel's bit for bit
+      p->tile_waves = lq::tckpt_waves(p->ts_nxp, p->ts_nup);
+      p->lds_tckpt = lq::tckpt_lds_bytes(p->ts_nxp, p->ts_nup, lt);
+      p->can_tile = lt <= kLdsLimit && p->lds_tckpt <= kLdsLimit;
+    }
   }
   p->variant = p->can_small ? VAR_SMALL : p->can_tile ? VAR_TILE : VAR_GENERIC;
   if (p->variant == VAR_GENERIC && !p->can_generic) {
@@ -266,10 +284,14 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     (void)hipGetLastError();
     p->can_tile = false;
   }
-  if (p->can_tile && lq::tsolve_sizes(p->maxnx, p->maxnu, &p->ts_nxp, &p->ts_nup) &&
+  if (p->can_tile && ckpt_stride == 0 && lq::tsolve_sizes(p->maxnx, p->maxnu, &p->ts_nxp, &p->ts_nup) &&
       lq::prepare_tsolve(p->ts_nxp, p->ts_nup, mode) != hipSuccess) {
     (void)hipGetLastError();
     p->ts_nxp = p->ts_nup = 0;
+  }
+  if (p->can_tile && ckpt_stride > 0 && lq::prepare_tckpt(p->ts_nxp, p->ts_nup, mode, p->lds_tckpt) != hipSuccess) {
+    (void)hipGetLastError();
+    p->can_tile = false;
   }
   if ((p->variant == VAR_GENERIC && !p->can_generic) || (p->variant == VAR_TILE && !p->can_tile)) {
     hipFree(p->desc_d);
@@ -410,6 +432,15 @@ static lq::SolveArgs base_args(const lq_plan* p, const lq_data* d, void* ws, con
   return a;
 }
 
+// Solve kernel of the plan's variant (the size-specialised one is dispatched by the caller).
+static hipError_t launch_solve_plan(const lq_plan* p, const lq::SolveArgs& a, void* ws, hipStream_t st) {
+  const lq::GenericLaunch c = generic_launch(p, ws, false);
+  if (p->variant == VAR_TILE && p->ckpt)
+    return lq::launch_solve_tckpt(p->ts_nxp, p->ts_nup, p->mode, a, p->lds_tckpt, c, st);
+  if (p->variant == VAR_TILE && p->ts_nxp) return lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, c, st);
+  return lq::launch_solve_generic(p->mode, a, p->lds_solve, c, st);
+}
+
 static int check_opts(const lq_solve_opts* o, const char* fn) {
   if (!o) return fail(LQ_EINVAL, "%s: opts is NULL", fn);
   if (!(o->tol >= 0.0)) return fail(LQ_EINVAL, "%s: tol must be >= 0", fn);
@@ -433,10 +464,8 @@ extern "C" int lq_solve(const lq_plan* p, const lq_data* d, void* ws, const lq_s
   hipError_t e;
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_solve_small(p->mode, p->N[0], p->nx[0], p->nu[0], a, st);
-  else if (p->variant == VAR_TILE && p->ts_nxp)
-    e = lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, generic_launch(p, ws, false), st);
   else
-    e = lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
+    e = launch_solve_plan(p, a, ws, st);
   return launch_status(e, "lq_solve");
 }
 
@@ -461,9 +490,7 @@ extern "C" int lq_solve_backward(const lq_plan* p, const lq_data* d, void* ws, c
   a.gx = gx; a.gu = gu;
   a.rhs = lq::RHS_ADJOINT;
   a.rel_res = rel_res; a.iters = iters; a.info = info;
-  hipError_t e = (p->variant == VAR_TILE && p->ts_nxp)
-                     ? lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, generic_launch(p, ws, false), st)
-                     : lq::launch_solve_generic(p->mode, a, p->lds_solve, generic_launch(p, ws, false), st);
+  hipError_t e = launch_solve_plan(p, a, ws, st);
   if ((rc = launch_status(e, "lq_solve_backward"))) return rc;
   lq::GradArgs g;
   g.desc = p->desc_d; g.batch = p->batch; g.d = *d;

@@ -74,10 +74,6 @@ __device__ void potrf_lds(double* H, int ld, int n, int ncol, double* dinv, int*
   __syncthreads();
 }
 
-// Checkpoint slot of stage k (k a multiple of the stride, or k = N) in an instance's factor
-// region; the segment buffer follows the slots.
-__device__ __forceinline__ int64_t ckpt_slots(int N, int s) { return N / s + 1 + (N % s ? 1 : 0); }
-__device__ __forceinline__ int64_t ckpt_slot(int k, int N, int s) { return k == N ? ckpt_slots(N, s) - 1 : k / s; }
 
 // Factor sweep of stages kb-1 down to ka of one instance by the whole workgroup, starting from
 // chol(Q_N) if kb = N, else from the stored L^Q_kb block `from`.  Stage k's block goes to
@@ -668,7 +664,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   red[tid] = v;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    if (tid < s) red[tid] = nan_max(red[tid], red[tid + s]);
     __syncthreads();
   }
   const double r = red[0];
@@ -706,8 +702,8 @@ __device__ void resid_init(const InstView& v, bool sweep, double* p2, double* sm
   for (int i = tid; i < nx; i += nt) {
     const double qi = rhs_q(v, N, i);
     const double rho = -qi - (ax[i] - v.lam[(int64_t)(N - 1) * nx + i]);
-    mr = fmax(mr, fabs(rho));
-    mb = fmax(mb, fabs(qi));
+    mr = nan_max(mr, fabs(rho));
+    mb = nan_max(mb, fabs(qi));
     pn[i] = -rho;
     if (sweep) p2[(int64_t)N * nx + i] = -rho;
   }
@@ -785,20 +781,20 @@ __device__ void resid_bwd(const InstView& v, const FactView<TF>& fv, bool sweep,
       const double ri = rhs_r(v, k, i);
       const double rho = -ri - au[i];
       au[i] = -rho;  // correction right-hand side r = -rho_u
-      mr = fmax(mr, fabs(rho));
-      mb = fmax(mb, fabs(ri + (k == 0 ? s0[i] : 0.0)));
+      mr = nan_max(mr, fabs(rho));
+      mb = nan_max(mb, fabs(ri + (k == 0 ? s0[i] : 0.0)));
     }
     for (int i = tid; i < nx; i += nt) {
       const double fi = rhs_f(v, k, i);
       const double rho = -fi - (al[i] - v.x[(int64_t)k * nx + i]);
-      mr = fmax(mr, fabs(rho));
-      mb = fmax(mb, fabs(fi + (k == 0 ? a0[i] : 0.0)));
+      mr = nan_max(mr, fabs(rho));
+      mb = nan_max(mb, fabs(fi + (k == 0 ? a0[i] : 0.0)));
       w[i] = -rho;
       if (k > 0) {
         const double qi = rhs_q(v, k, i);
         const double rho2 = -qi - (ax[i] - v.lam[(int64_t)(k - 1) * nx + i]);
-        mr = fmax(mr, fabs(rho2));
-        mb = fmax(mb, fabs(qi));
+        mr = nan_max(mr, fabs(rho2));
+        mb = nan_max(mb, fabs(qi));
         ax[i] = -rho2;  // q = -rho_x
       }
     }
@@ -858,7 +854,7 @@ __device__ void resid_bwd(const InstView& v, const FactView<TF>& fv, bool sweep,
 __device__ __forceinline__ double resid_final(double mr, double mb, double* red) {
   mr = block_max(mr, red);
   mb = block_max(mb, red);
-  return mb > 0.0 ? mr / mb : mr;
+  return rel_of(mr, mb);
 }
 
 template <typename TF>

@@ -44,6 +44,13 @@ __host__ __device__ inline int64_t v2_rhox(int64_t N, int64_t nx, int64_t nu) {
   return 2 * N * nu + (N + 1) * nx + N * nx;
 }
 
+// Factor region of a checkpointed instance (stride s): one slot per stage 0, s, 2s, ... and N,
+// then a segment buffer of s stage blocks.  ckpt_slot(k) is the slot of such a stage k.
+__host__ __device__ inline int64_t ckpt_slots(int64_t N, int64_t s) { return N / s + 1 + (N % s ? 1 : 0); }
+__host__ __device__ inline int64_t ckpt_slot(int64_t k, int64_t N, int64_t s) {
+  return k == N ? ckpt_slots(N, s) - 1 : k / s;
+}
+
 // LDS layout of the tile factor kernel (byte offsets) for TU input and TX state tiles of 16:
 // U^Q tiles of the state block (TX(TX+1)/2, factor type), input-pivot panels (TU x T float64
 // tiles), state-pivot panels (mixed: 2 x T float64 tiles; float64 mode keeps them in the U^Q
@@ -78,6 +85,13 @@ __host__ __device__ inline TileLds tile_lds(int TU, int TX, bool f64) {
   o += 8 * (48 * TX + 32 * T + 16 * TU);
   L.total = o;
   return L;
+}
+
+// Maximum that propagates NaN (fmax would drop it and hide a non-finite residual), and the
+// relative residual max|rho| / max|b| from the two maxima (NaN if either is).
+__device__ __forceinline__ double nan_max(double m, double v) { return (v > m || v != v) ? v : m; }
+__device__ __forceinline__ double rel_of(double mr, double mb) {
+  return mb != mb ? mb : (mb > 0.0 ? mr / mb : mr);
 }
 
 // Right-hand side selector of the solve kernels.

@@ -85,10 +85,10 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double rowmax(double v) {
-  v = fmax(v, dpp_d<0xB1>(v));
-  v = fmax(v, dpp_d<0x4E>(v));
-  v = fmax(v, dpp_d<0x124>(v));
-  v = fmax(v, dpp_d<0x128>(v));
+  v = nan_max(v, dpp_d<0xB1>(v));
+  v = nan_max(v, dpp_d<0x4E>(v));
+  v = nan_max(v, dpp_d<0x124>(v));
+  v = nan_max(v, dpp_d<0x128>(v));
   return v;
 }
 
@@ -656,15 +656,15 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       const double rhol = -fo - (al[0] + al[1]);
       const double rhox = -rq - ((ax[0] + ax[1]) + abt);
       if (ul) {
-        mr = fmax(mr, fabs(rhou));
-        mb = fmax(mb, fabs(rq + bu));
+        mr = nan_max(mr, fabs(rhou));
+        mb = nan_max(mb, fabs(rq + bu));
       }
       if (xl) {
-        mr = fmax(mr, fabs(rhol));
-        mb = fmax(mb, fabs(fo + bl));
+        mr = nan_max(mr, fabs(rhol));
+        mb = nan_max(mb, fabs(fo + bl));
         if (k > 0) {
-          mr = fmax(mr, fabs(rhox));
-          mb = fmax(mb, fabs(rq));
+          mr = nan_max(mr, fabs(rhox));
+          mb = nan_max(mb, fabs(rq));
         }
       }
       if (store) {
@@ -693,13 +693,13 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     const double qv = s.d.q[(bb * (N + 1) + N) * NX + mi];
     const double rhox = -qv - ax;
     if (xl) {
-      mr = fmax(mr, fabs(rhox));
-      mb = fmax(mb, fabs(qv));
+      mr = nan_max(mr, fabs(rhox));
+      mb = nan_max(mb, fabs(qv));
       if (store) s.rhox[(int64_t)N * NX + mi] = rhox;
     }
     mr = rowmax(mr);
     mb = rowmax(mb);
-    return mb > 0.0 ? mr / mb : mr;
+    return rel_of(mr, mb);
   }
   return 0.0;
 }

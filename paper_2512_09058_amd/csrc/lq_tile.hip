@@ -1,193 +1,8 @@
-// Matrix-core tile kernel of the factor sweep for medium and large stage sizes.
-//
-// One workgroup per instance (or a persistent grid pulling instances longest first), one
-// wavefront per 16-wide tile column of the stage matrix.  The input block and the state block
-// are each padded to a multiple of 16 (TU = ceil(nu/16), TX = ceil(nx/16) tiles, T = TU + TX)
-// with an identity diagonal and zero coupling, which leaves the factors of the real rows and
-// columns unchanged.
-//
-// Per stage, backward in time (paper, Alg. "factor-block-column-riccati" with one interval):
-//   W = V^T = (L^Q_{k+1})^T C,  C = [B_k A_k]                   (trmm, nx x nux)
-//   Hhat = [[R,S],[S^T,Q]] + W^T W                              (syrk)
-//   chol(Hhat) = [[L^R, 0],[L^S, L^Q]]                           (blocked potrf, float64)
-// Matrix-core layout: a 16x16 fragment of a 64-lane wavefront holds element (row(t), c) of the
-// tile in slot t of lane 16 g + c, with row(t) = 4t + g for float64 and 4g + t for float32
-// products.  That layout is also the B operand of the next product when the contraction index
-// of instruction s is row(s), so every product here has the form Y += op(M) X with X a fragment
-// in registers and M a tile in LDS.  Wavefront a owns tile column a: its C tiles C(m', a), its
-// W tiles W(m, a) and the upper tiles G(b, a) = Hhat(b, a), b <= a.
-//   trmm   W(m, a)  = sum_{m' >= m} U^Q(m, m') C(m', a)   with U^Q = (L^Q_{k+1})^T in LDS,
-//   syrk   G(b, a) += W(m, b)^T W(m, a), streamed over 16-row slabs m of W through LDS,
-//   potrf  per pivot tile j: the owner of column j factors G(j, j) (row per lane, DPP
-//          broadcasts, float64) and inverts it; the owners of columns a > j form
-//          U(j, a) = L_jj^{-1} G(j, a) = L(a, j)^T on the matrix cores and publish it in LDS;
-//          then G(b, a) -= U(j, b)^T U(j, a) for j < b <= a.
-// The tiles U(j, a) of the state block are L^Q_k transposed: they stay in LDS as the U^Q operand
-// of the next stage.  The right-hand-side sweep (rbar_k, p_k) runs in float64 beside it, as in
-// the other factor kernels, and the factor blocks use the shared workspace layout.
-//
-// Precision: TP is the type of the stage products: float64; float32 (mixed mode: operands the
-// float32-rounded L^Q and C, float32 accumulation); or bf16 operands with float32 accumulation
-// (rounded from the float32 L^Q, C and W).  The potrf and everything after it is float64 and the
-// factors are rounded to TF for storage.
-#include <math.h>
-
-#include <type_traits>
-
-#include "lq_internal.hpp"
+// Matrix-core tile factor kernel (the sweep itself is in lq_tile_factor.hpp) and its host side.
+#include "lq_tile_factor.hpp"
 
 namespace lq {
 namespace {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double rsqrt_f64(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-  const double h = 0.5 * a;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
-}
-
-// Broadcast lane k of each 16-lane row to the whole row (k a constant after unrolling).
-__device__ __forceinline__ double bc(double v, int k) {
-  long x = __double_as_longlong(v);
-  switch (k) {
-#define BC(K) \
-  case K:     \
-    x = __builtin_amdgcn_update_dpp((long)0, x, 0x150 + K, 0xF, 0xF, true); \
-    break;
-    BC(0) BC(1) BC(2) BC(3) BC(4) BC(5) BC(6) BC(7) BC(8) BC(9) BC(10) BC(11) BC(12) BC(13) BC(14) BC(15)
-#undef BC
-  }
-  return __longlong_as_double(x);
-}
-
-// Order the LDS accesses of one wavefront (its DS operations complete in issue order).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-  __builtin_amdgcn_wave_barrier();
-}
-
-template <typename TP>
-struct MM;
-template <>
-struct MM<double> {
-  typedef d4 V;
-  static __device__ __forceinline__ int row(int t, int g) { return 4 * t + g; }
-  static __device__ __forceinline__ V mma(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct MM<float> {
-  typedef f4 V;
-  static __device__ __forceinline__ int row(int t, int g) { return 4 * g + t; }
-  static __device__ __forceinline__ V mma(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-
-// bf16 operands with float32 accumulation: one 16x16x16 instruction per tile product.  Operand
-// slot i of lane 16 g + c holds contraction index 4 g + i, so a float32 fragment (row 4g + t in
-// slot t) is directly the B operand and the A operand is four consecutive entries of a row.
-struct BF16 {};
-typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-template <>
-struct MM<BF16> {
-  typedef f4 V;
-  static __device__ __forceinline__ int row(int t, int g) { return 4 * g + t; }
-};
-
-// Element type of W slabs and of converted C fragments for a product type.
-template <typename TP>
-struct Elem {
-  typedef TP type;
-};
-template <>
-struct Elem<BF16> {
-  typedef float type;
-};
-
-// Leading dimensions of LDS tiles (padded against bank conflicts; float rows stay 16-byte aligned).
-template <typename T>
-struct Ld;
-template <>
-struct Ld<double> {
-  static constexpr int v = 17;
-};
-template <>
-struct Ld<float> {
-  static constexpr int v = 20;
-};
-
-// acc += op(M) X for a 16x16 LDS tile M (leading dimension ld) and a fragment X;
-// TR = false: op(M) = M, TR = true: op(M) = M^T.  NEG subtracts.
-template <typename TP, bool TR, bool NEG = false, typename TM>
-__device__ __forceinline__ typename MM<TP>::V tmm(typename MM<TP>::V acc, const TM* M, int ld,
-                                                   const typename MM<TP>::V& X, int g, int c) {
-  if constexpr (std::is_same<TP, BF16>::value) {
-    b4 av, bv;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float m = (float)(TR ? M[(4 * g + i) * ld + c] : M[c * ld + 4 * g + i]);
-      av[i] = (__bf16)(NEG ? -m : m);
-      bv[i] = (__bf16)X[i];
-    }
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-  } else {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = MM<TP>::row(s, g);
-      TP av = (TP)(TR ? M[kk * ld + c] : M[c * ld + kk]);
-      if (NEG) av = -av;
-      acc = MM<TP>::mma(av, X[s], acc);
-    }
-    return acc;
-  }
-}
-
-// Right-looking Cholesky of a 16x16 tile held one row per lane (lane c of each 16-lane row:
-// row c in h).  Returns 0, 1 (a pivot was not positive) or 2 (not finite); failed pivots are
-// replaced by 1.  On return h[0..c] is row c of L and dinv = 1 / L[c][c].
-__device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c) {
-  bool ok = true, fin = true;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double dj = bc(h[j], j);
-    const bool pos = dj > 0.0;
-    ok = ok && pos;
-    fin = fin && isfinite(dj);
-    dj = pos ? dj : 1.0;
-    const double inv = rsqrt_f64(dj);
-    h[j] = (c == j) ? dj * inv : h[j] * inv;
-    dinv = (c == j) ? inv : dinv;
-#pragma unroll
-    for (int kk = j + 1; kk < 16; ++kk) h[kk] = fma(-h[j], bc(h[j], kk), h[kk]);
-  }
-  return ok ? 0 : (fin ? 1 : 2);
-}
-
-// Column c of X = L^{-1} for the lower-triangular 16x16 L in LDS (row-major, leading dimension
-// ld) with reciprocal diagonal di: forward substitution, entirely within the lane (the entries of
-// L are the same for every lane).  x[r] = X[r][c].
-__device__ __forceinline__ void inv16_col(double (&x)[16], const double* Lt, int ld, const double* di, int c) {
-#pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = r == c ? 1.0 : 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    x[k] *= di[k];
-#pragma unroll
-    for (int r = k + 1; r < 16; ++r) x[r] = fma(-Lt[r * ld + k], x[k], x[r]);
-  }
-}
-
-// Element q = 4 g + qq of a 16-element per-lane row, for the lane's group g.
-__device__ __forceinline__ double pick4(const double (&v)[16], int g, int qq) {
-  const double a0 = v[qq], a1 = v[4 + qq], a2 = v[8 + qq], a3 = v[12 + qq];
-  return g == 0 ? a0 : g == 1 ? a1 : g == 2 ? a2 : a3;
-}
 
 // Instances of this workgroup: without a counter the one at position blockIdx.x, with a counter
 // positions pulled from it until the batch is exhausted (every workgroup exits once the counter
@@ -210,365 +25,6 @@ __device__ __forceinline__ void for_each_instance(int batch, const int32_t* orde
   }
 }
 
-template <int TMAX, typename TF, typename TP>
-__device__ __forceinline__ void factor_tile_one(const Desc& D, const lq_data& d, TF* __restrict__ Fi, double* __restrict__ Vi,
-                                unsigned char* lds, int& s_info) {
-  constexpr bool F64 = std::is_same<TP, double>::value;
-  typedef typename MM<TP>::V PV;
-  typedef typename Elem<TP>::type TE;  // W slabs, converted C fragments
-  constexpr int LQ = Ld<TF>::v, LW = Ld<TE>::v, LD = Ld<double>::v;
-  const int N = D.N, nx = D.nx, nu = D.nu;
-  const int TU = (nu + 15) >> 4, TX = (nx + 15) >> 4, T = TU + TX;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront index (uniform)
-  const bool own = w < T;
-  const int a = w;
-  const TileLds L = tile_lds(TU, TX, F64);
-  TF* LQB = (TF*)(lds + L.oLQB);
-  double* UP = (double*)(lds + L.oUP);
-  double* XP = (double*)(lds + L.oXP);
-  TE* WS = (TE*)(lds + L.oWS);
-  double* DI = (double*)(lds + L.oDI);
-  double* SC = (double*)(lds + L.oSC);
-  // per-wavefront relayout tile of the mixed mode, in the slab region (dead at that point)
-  double* CV = (double*)(lds + L.oXP) + w * 16 * LD;
-  double* pv = (double*)(lds + L.oVec);  // p_{k+1}, then p_k   [16 TX]
-  double* wv = pv + 16 * TX;             // w                   [16 TX]
-  double* t1 = wv + 16 * TX;             //                     [16 TX]
-  double* rq = t1 + 16 * TX;             // (rhat, qhat)        [16 T]
-  double* dv = rq + 16 * T;              // 1 / diag of L       [16 T]
-  double* rb = dv + 16 * T;              // rbar                [16 TU]
-  // U^Q tile (m, m'), m <= m' (state block), row-major; panels U(j, a), a >= j
-  auto lqb = [&](int m, int mp) { return LQB + (mp * (mp + 1) / 2 + m) * 16 * LQ; };
-  auto upan = [&](int j, int aa) { return UP + (j * T + aa) * 16 * LD; };
-  auto xpan = [&](int j, int aa) -> double* {
-    if constexpr (F64) return (double*)lqb(j - TU, aa - TU);
-    else return XP + ((j & 1) * T + aa) * 16 * LD;
-  };
-  auto pan = [&](int j, int aa) { return j < TU ? upan(j, aa) : xpan(j, aa); };
-  auto wsl = [&](int m, int aa) { return WS + ((m & 1) * T + aa) * 16 * LW; };
-
-  const int64_t fs = stage_factor_elems(nx, nu);
-  const int oDR = off_dR(nx, nu), oLS = off_LS(nx, nu), oLQ = off_LQ(nx, nu), oDQ = off_dQ(nx, nu);
-  const double* Ag = d.A + D.oA;
-  const double* Bg = d.B + D.oB;
-  const double* Qg = d.Q + D.oQ;
-  const double* Rg = d.R + D.oR;
-  const double* Sg = d.S ? d.S + D.oS : nullptr;
-  const double* qg = d.q + D.oq;
-  const double* rg = d.r + D.or_;
-  const double* fg = d.f ? d.f + D.of : nullptr;
-  double* rbar_g = Vi;
-  double* p_g = Vi + (int64_t)N * nu;
-
-  if (tid == 0) s_info = 0;
-  for (int i = tid; i < 16 * TX; i += nt) {
-    const double v = i < nx ? qg[(int64_t)N * nx + i] : 0.0;
-    pv[i] = v;
-    if (i < nx) p_g[(int64_t)N * nx + i] = v;
-  }
-  __syncthreads();
-
-  for (int k = N; k >= 0; --k) {
-    // Lane coordinates re-derived per stage from an opaque copy of the thread index: without it
-    // the compiler hoists every per-lane address and select of the unrolled tile loops out of the
-    // stage loop and runs out of registers.
-    int ltid = tid;
-    asm volatile("" : "+v"(ltid));
-    const int lane = ltid & 63, g = lane >> 4, c = lane & 15;
-    const double* Ak = Ag + (int64_t)k * nx * nx;
-    const double* Bk = Bg + (int64_t)k * nx * nu;
-    const double* Qk = Qg + (int64_t)k * nx * nx;
-    const double* Rk = Rg + (int64_t)k * nu * nu;
-    const double* Sk = Sg ? Sg + (int64_t)k * nu * nx : nullptr;
-    // Symmetric part of [[R,S],[S^T,Q]] (padded) in the float64 fragment layout, tile (bb, aa):
-    // at stage N only the state block (Q_N), at stage 0 only the input rows.
-    auto load_h = [&](int bb, int aa) -> d4 {
-      // branch-free within the wavefront: clamped addresses, out-of-range entries selected away
-      d4 h = d4{0, 0, 0, 0};
-      const bool bu = bb < TU, au = aa < TU;
-      const int ib = (bu ? 16 * bb : 16 * (bb - TU)) + g, jb = (au ? 16 * aa : 16 * (aa - TU)) + c;
-      if (bu && au) {
-        if (k < N) {
-          const int jc = min(jb, nu - 1);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int ii = ib + 4 * t, ic = min(ii, nu - 1);
-            const double v = 0.5 * (Rk[ic * nu + jc] + Rk[jc * nu + ic]);
-            h[t] = (ii < nu && jb < nu) ? v : (ii == jb ? 1.0 : 0.0);
-          }
-        }
-      } else if (bu) {
-        if (k < N && Sk) {
-          const int jc = min(jb, nx - 1);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int ii = ib + 4 * t, ic = min(ii, nu - 1);
-            const double v = Sk[ic * nx + jc];
-            h[t] = (ii < nu && jb < nx) ? v : 0.0;
-          }
-        }
-      } else if (k > 0) {
-        const int jc = min(jb, nx - 1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ii = ib + 4 * t, ic = min(ii, nx - 1);
-          const double v = 0.5 * (Qk[ic * nx + jc] + Qk[jc * nx + ic]);
-          h[t] = (ii < nx && jb < nx) ? v : (ii == jb ? 1.0 : 0.0);
-        }
-      }
-      return h;
-    };
-
-    d4 G[TMAX];
-#pragma unroll
-    for (int bb = 0; bb < TMAX; ++bb) G[bb] = d4{0, 0, 0, 0};
-    if (k == N) {
-      if (own) {
-#pragma unroll
-        for (int bb = 0; bb < TMAX; ++bb)
-          if (bb <= a) G[bb] = load_h(bb, a);
-      }
-    } else {
-      // ---- w = L^Q_{k+1} (L^Q_{k+1})^T f_k + p_{k+1}
-      if (fg) {
-        const double* fk = fg + (int64_t)k * nx;
-        for (int j = tid; j < nx; j += nt) {
-          double s = 0.0;
-          for (int i = j; i < nx; ++i) s += (double)lqb(j >> 4, i >> 4)[(j & 15) * LQ + (i & 15)] * fk[i];
-          t1[j] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < 16 * TX; i += nt) {
-          double s = pv[i];
-          if (i < nx)
-            for (int j = 0; j <= i; ++j) s += (double)lqb(j >> 4, i >> 4)[(j & 15) * LQ + (i & 15)] * t1[j];
-          wv[i] = s;
-        }
-      } else {
-        for (int i = tid; i < 16 * TX; i += nt) wv[i] = pv[i];
-      }
-      __syncthreads();
-      // ---- C tiles of column a (float64 for (rhat, qhat) = (r, q) + C^T w, TP for the trmm)
-      // ---- trmm + syrk, streamed over the 16-row slabs m of W.  The fragments C(m', a) are read
-      // from global memory two tiles ahead (cache-resident after the first slab); the first slab,
-      // which touches every C tile once, also accumulates (C^T w)_a in float64.
-      const bool ucol = a < TU;
-      const int col = ucol ? 16 * a + c : 16 * (a - TU) + c;
-      const int ldc = ucol ? nu : nx;
-      const int ncol = ucol ? nu : nx;
-      const bool colok = col < ncol;
-      const int r0 = MM<TP>::row(0, g);  // row(t, g) = r0 + row(t, 0)
-      const double* cb = (ucol ? Bk : Ak) + min(col, ncol - 1);
-      auto load_c = [&](int mp) -> d4 {
-        d4 v;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int row = r0 + 16 * mp + MM<TP>::row(t, 0);
-          const double e = cb[min(row, nx - 1) * ldc];
-          v[t] = (colok && row < nx) ? e : 0.0;
-        }
-        return v;
-      };
-      PV Gs[TMAX];
-#pragma unroll
-      for (int bb = 0; bb < TMAX; ++bb) Gs[bb] = PV{0, 0, 0, 0};
-      double part = 0.0;
-      for (int m = 0; m < TX; ++m) {
-        PV Wf = PV{0, 0, 0, 0};
-        if (own) {
-          d4 cur = load_c(m);
-          d4 nxt = m + 1 < TX ? load_c(m + 1) : d4{0, 0, 0, 0};
-          for (int mp = m; mp < TX; ++mp) {
-            const d4 nn = mp + 2 < TX ? load_c(mp + 2) : d4{0, 0, 0, 0};
-            if (m == 0) {
-#pragma unroll
-              for (int t = 0; t < 4; ++t) part = fma(cur[t], wv[16 * mp + r0 + MM<TP>::row(t, 0)], part);
-            }
-            PV cx;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) cx[t] = (TE)cur[t];
-            Wf = tmm<TP, false>(Wf, lqb(m, mp), LQ, cx, g, c);
-            cur = nxt;
-            nxt = nn;
-          }
-          TE* ws = wsl(m, a);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) ws[MM<TP>::row(t, g) * LW + c] = Wf[t];
-        }
-        __syncthreads();
-        if (own) {
-#pragma unroll
-          for (int bb = 0; bb < TMAX; ++bb)
-            if (bb <= a && (k > 0 || bb < TU)) Gs[bb] = tmm<TP, true>(Gs[bb], wsl(m, bb), LW, Wf, g, c);
-        }
-      }
-      __syncthreads();
-      if (own) {
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (g == 0) {
-          double base = 0.0;
-          if (ucol) {
-            if (col < nu) base = rg[(int64_t)k * nu + col];
-          } else if (k > 0 && col < nx) {
-            base = qg[(int64_t)k * nx + col];
-          }
-          rq[16 * a + c] = base + part;
-        }
-      }
-      // ---- G = [[R,S],[S^T,Q]] + W^T W in float64 (mixed: float32 layout -> float64 layout)
-      if (own) {
-#pragma unroll
-        for (int bb = 0; bb < TMAX; ++bb) {
-          if (bb <= a) {
-            const d4 h = load_h(bb, a);
-            if constexpr (F64) {
-              G[bb] = h + Gs[bb];
-            } else {
-#pragma unroll
-              for (int t = 0; t < 4; ++t) CV[MM<TP>::row(t, g) * LD + c] = (double)Gs[bb][t];
-              wave_sync();
-#pragma unroll
-              for (int t = 0; t < 4; ++t) G[bb][t] = h[t] + CV[MM<double>::row(t, g) * LD + c];
-              wave_sync();
-            }
-          }
-        }
-      }
-    }
-
-    // ---- blocked potrf over the pivot tiles [j0, j1)
-    const int j0 = k == N ? TU : 0, j1 = k == 0 ? TU : T;
-    for (int j = j0; j < j1; ++j) {
-      if (own && a == j) {
-        // lane coordinates re-derived here so that the diagonal step's per-lane addresses and
-        // masks are not kept live across the whole pivot loop
-        int dt = tid;
-        asm volatile("" : "+v"(dt));
-        const int lane = dt & 63, g = lane >> 4, c = lane & 15;
-        d4 Gj = G[0];
-#pragma unroll
-        for (int bb = 1; bb < TMAX; ++bb)
-          if (bb == j) Gj = G[bb];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) SC[MM<double>::row(t, g) * LD + c] = Gj[t];
-        wave_sync();
-        double dinv = 0.0;
-        {
-          double h[16];
-#pragma unroll
-          for (int q = 0; q < 16; ++q) h[q] = SC[c * LD + q];
-          const int bad = chol16(h, dinv, c);
-          if (bad && lane == 0 && s_info == 0) s_info = bad == 2 ? LQ_INFO_NONFINITE : k + 1;
-          wave_sync();
-          // L_jj row-major into the scratch tile (for the inverse), U(j, j) = L_jj^T into its
-          // panel / the L^Q tiles
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) {
-            const int q = 4 * g + qq;
-            const double l = q <= c ? pick4(h, g, qq) : 0.0;
-            SC[c * LD + q] = l;
-            if (j < TU) upan(j, j)[q * LD + c] = l;
-            else lqb(j - TU, j - TU)[q * LQ + c] = (TF)l;
-          }
-          if (g == 0) dv[16 * j + c] = dinv;
-          wave_sync();
-        }
-        {
-          // X = L_jj^{-1}; DI holds X^T row-major (row c = column c of X)
-          double x[16];
-          inv16_col(x, SC, LD, dv + 16 * j, c);
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) DI[c * LD + 4 * g + qq] = pick4(x, g, qq);
-        }
-        // column j is complete: none of its tiles is read again, and redefining them here lets
-        // the diagonal step reuse their registers
-#pragma unroll
-        for (int bb = 0; bb < TMAX; ++bb) G[bb] = d4{0, 0, 0, 0};
-      }
-      __syncthreads();
-      d4 Uf = d4{0, 0, 0, 0};
-      if (own && a > j) {
-#pragma unroll
-        for (int bb = 0; bb < TMAX; ++bb)
-          if (bb == j) Uf = tmm<double, true>(Uf, DI, LD, G[bb], g, c);
-        double* P = pan(j, a);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) P[MM<double>::row(t, g) * LD + c] = Uf[t];
-        if constexpr (!F64) {
-          if (j >= TU) {
-            TF* Qt = lqb(j - TU, a - TU);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) Qt[MM<double>::row(t, g) * LQ + c] = (TF)Uf[t];
-          }
-        }
-      }
-      __syncthreads();
-      if (own && a > j) {
-#pragma unroll
-        for (int bb = 0; bb < TMAX; ++bb)
-          if (bb > j && bb <= a && (k > 0 || bb < TU)) G[bb] = tmm<double, true, true>(G[bb], pan(j, bb), LD, Uf, g, c);
-      }
-    }
-    __syncthreads();
-
-    // ---- rbar_k = (L^R_k)^{-1} rhat,  p_k = qhat - L^S_k rbar_k (rounded factors, float64)
-    if (k < N) {
-      if (w == 0) {
-        // one row per lane, 64 rows per pass
-        for (int i0 = 0; i0 < nu; i0 += 64) {
-          const int i = i0 + lane;
-          double acc = i < nu ? rq[i] : 0.0;
-          const double di = i < nu ? (double)(TF)dv[i] : 0.0;
-          // contributions of the rows of earlier passes
-          for (int jj = 0; jj < i0; ++jj)
-            if (i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * rb[jj];
-          for (int jj = i0; jj < nu && jj < i0 + 64; ++jj) {
-            const double y = __shfl(acc * di, jj - i0);
-            if (i > jj && i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * y;
-          }
-          if (i < nu) {
-            const double v = acc * di;
-            rb[i] = v;
-            rbar_g[(int64_t)k * nu + i] = v;
-          }
-          wave_sync();
-        }
-      }
-      __syncthreads();
-      if (k > 0) {
-        for (int i = tid; i < nx; i += nt) {
-          double s = rq[16 * TU + i];
-          for (int jj = 0; jj < nu; ++jj)
-            s -= (double)(TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)] * rb[jj];
-          pv[i] = s;
-          p_g[(int64_t)k * nx + i] = s;
-        }
-      }
-    }
-    // ---- factor block of stage k (coalesced, from LDS)
-    TF* Fk = Fi + (int64_t)k * fs;
-    if (k < N) {
-      for (int i = w; i < nu; i += nt >> 6)
-        for (int jj = lane; jj <= i; jj += 64)
-          Fk[i * (i + 1) / 2 + jj] = (TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)];
-      for (int i = tid; i < nu; i += nt) Fk[oDR + i] = (TF)dv[i];
-      for (int e = tid; e < nx * nu; e += nt) {
-        const int i = e / nu, jj = e - i * nu;
-        Fk[oLS + e] = (TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)];
-      }
-    }
-    if (k > 0) {
-      for (int i = w; i < nx; i += nt >> 6)
-        for (int jj = lane; jj <= i; jj += 64)
-          Fk[oLQ + i * (i + 1) / 2 + jj] = lqb(jj >> 4, i >> 4)[(jj & 15) * LQ + (i & 15)];
-      for (int i = tid; i < nx; i += nt) Fk[oDQ + i] = (TF)dv[16 * TU + i];
-    }
-    __syncthreads();
-  }
-}
-
 // Wavefronts per SIMD the register allocation targets: enough resident workgroups that several
 // instances share a CU (their latency chains overlap).
 template <int TMAX>
@@ -581,12 +37,19 @@ __global__ void __launch_bounds__(64 * TMAX) __attribute__((amdgpu_waves_per_eu(
 k_factor_tile(const Desc* __restrict__ desc, int batch, lq_data d,
                                                           TF* __restrict__ F, double* __restrict__ Vws,
                                                           int32_t* __restrict__ info, const int32_t* __restrict__ order,
-                                                          int32_t* counter) {
+                                                          int32_t* counter, int ckpt) {
   extern __shared__ __align__(16) unsigned char lds_tile[];
   __shared__ int s_info;
   for_each_instance(batch, order, counter, [&](int b) {
     const Desc D = desc[b];
-    factor_tile_one<TMAX, TF, TP>(D, d, F + D.oF, Vws + D.oV, lds_tile, s_info);
+    // every stage block stored, or with a checkpoint stride only those of stages 0, s, 2s, ..., N
+    TF* Fi = F + D.oF;
+    const int64_t fs = stage_factor_elems(D.nx, D.nu);
+    auto dst = [&](int k) -> TF* {
+      if (ckpt == 0) return Fi + (int64_t)k * fs;
+      return (k % ckpt == 0 || k == D.N) ? Fi + ckpt_slot(k, D.N, ckpt) * fs : nullptr;
+    };
+    factor_tile_range<TMAX, TF, TP>(D, d, 0, D.N, dst, (const TF*)nullptr, Vws + D.oV, lds_tile, s_info);
     if (threadIdx.x == 0) info[b] = s_info;
     __syncthreads();
   });
@@ -608,13 +71,13 @@ hipError_t launch_tile(lq_mode mode, dim3 grid, dim3 block, size_t lds, hipStrea
                        const lq_data& d, void* F, double* V, int32_t* info, const GenericLaunch& c) {
   if (mode == LQ_F64)
     hipLaunchKernelGGL((k_factor_tile<TMAX, double, double>), grid, block, lds, st, desc, batch, d, (double*)F, V,
-                       info, c.order, c.counter);
+                       info, c.order, c.counter, c.ckpt);
   else if (mode == LQ_MIXED_BF16)
     hipLaunchKernelGGL((k_factor_tile<TMAX, float, BF16>), grid, block, lds, st, desc, batch, d, (float*)F, V, info,
-                       c.order, c.counter);
+                       c.order, c.counter, c.ckpt);
   else
     hipLaunchKernelGGL((k_factor_tile<TMAX, float, float>), grid, block, lds, st, desc, batch, d, (float*)F, V,
-                       info, c.order, c.counter);
+                       info, c.order, c.counter, c.ckpt);
   return hipGetLastError();
 }
 

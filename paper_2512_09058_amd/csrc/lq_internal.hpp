@@ -87,6 +87,16 @@ __host__ __device__ inline TileLds tile_lds(int TU, int TX, bool f64) {
   return L;
 }
 
+// c ? v : 0 without control flow.  Written as a select, the compiler turns a load feeding it into
+// a load under a divergent branch, and the end of that branch waits for every load in flight,
+// which serialises loads meant to overlap.  The mask here is opaque to the optimiser, so the load
+// (from a clamped, always valid address) stays unconditional and its wait moves to the first use.
+__device__ __forceinline__ double keep_if(bool c, double v) {
+  int m = c ? -1 : 0;
+  asm volatile("" : "+v"(m));
+  return __longlong_as_double(__double_as_longlong(v) & (long long)m);
+}
+
 // Maximum that propagates NaN (fmax would drop it and hide a non-finite residual), and the
 // relative residual max|rho| / max|b| from the two maxima (NaN if either is).
 __device__ __forceinline__ double nan_max(double m, double v) { return (v > m || v != v) ? v : m; }

@@ -4,9 +4,10 @@
 namespace lq {
 namespace {
 
+// Register target: two wavefronts per SIMD (several instances per CU hide each other's latency).
 template <int W, int NXP, int NUP, typename TF>
-__global__ void __launch_bounds__(64 * W) k_solve_tile(SolveArgs a, const int32_t* __restrict__ order,
-                                                       int32_t* counter) {
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2)))
+k_solve_tile(SolveArgs a, const int32_t* __restrict__ order, int32_t* counter) {
   extern __shared__ double sm_ts[];
   each_instance(a.batch, order, counter, [&](int b) { tsolve_one<W, NXP, NUP, TF>(a, b, sm_ts); });
 }

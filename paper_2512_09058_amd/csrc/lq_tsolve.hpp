@@ -86,15 +86,44 @@ __device__ __forceinline__ void frag_load(Frag<R, C, CW>& f, const T* __restrict
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = frag_col<CW>(L, c);
-      const double e = (double)M[(r < nr ? r : nr - 1) * ld + (j < nc ? j : nc - 1)];
-      f.v[t][c] = (r < nr && j < nc) ? e : 0.0;
+      const double e = (double)M[(uint32_t)((r < nr ? r : nr - 1) * ld + (j < nc ? j : nc - 1))];
+      f.v[t][c] = keep_if(r < nr && j < nc, e);
     }
   }
 }
 
-__device__ __forceinline__ double xor_sum(double a, int from, int to) {
-  for (int o = from; o < to; o <<= 1) a += __shfl_xor(a, o);
-  return a;
+// Lane reductions without LDS-unit shuffles: DPP moves inside rows of 16 lanes (quad swaps, then
+// the half-row and row mirrors, which pair each lane with one holding the other half's partial
+// sum), then the row-pair and half-wave swaps of v_permlane16/32_swap.  lane_sum<F, T> sums over
+// the lanes that differ only in the index bits from F up to T (F, T powers of two; the mirror
+// steps need F = 1 when T > 4).  Every lane ends with the same value (each step adds its own
+// partial and its partner's, a commutative pair).  Called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  return __longlong_as_double(__builtin_amdgcn_update_dpp(0LL, __double_as_longlong(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double swap_sum16(double v) {
+  const unsigned lo = (unsigned)__double_as_longlong(v), hi = (unsigned)(__double_as_longlong(v) >> 32);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double swap_sum32(double v) {
+  const unsigned lo = (unsigned)__double_as_longlong(v), hi = (unsigned)(__double_as_longlong(v) >> 32);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+template <int F, int T>
+__device__ __forceinline__ double lane_sum(double v) {
+  static_assert(F == 1 || F >= 16 || T <= 4, "mirror steps need the lower lanes reduced");
+  if constexpr (F <= 1 && T > 1) v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (F <= 2 && T > 2) v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (F <= 4 && T > 4) v += dpp_mov<0x141>(v);  // row_half_mirror
+  if constexpr (F <= 8 && T > 8) v += dpp_mov<0x140>(v);  // row_mirror
+  if constexpr (F <= 16 && T > 16) v = swap_sum16(v);
+  if constexpr (F <= 32 && T > 32) v = swap_sum32(v);
+  return v;
 }
 
 // out(r, (M x)_r) for the rows held; x is a zero-padded LDS vector.
@@ -106,7 +135,7 @@ __device__ __forceinline__ void frag_rows(const Frag<R, C, CW>& f, const double*
     double p = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) p = fma(f.v[t][c], x[frag_col<CW>(L, c)], p);
-    p = xor_sum(p, 1, CW);
+    p = lane_sum<1, CW>(p);
     const int r = frag_row<R, C, CW>(L, W, t);
     if ((L.lane % CW) == 0 && r < nr) out(r, p);
   }
@@ -139,11 +168,11 @@ __device__ __forceinline__ void stream_sq(const double* __restrict__ M, int nr, 
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = frag_col<CW>(L, c);
-      const double e = M[rc * nr + (j < nr ? j : nr - 1)];
-      v[c] = (r < nr && j < nr) ? e : 0.0;
+      const double e = M[(uint32_t)(rc * nr + (j < nr ? j : nr - 1))];
+      v[c] = keep_if(r < nr && j < nr, e);
       p = fma(v[c], x[j], p);
     }
-    p = xor_sum(p, 1, CW);
+    p = lane_sum<1, CW>(p);
     if ((L.lane % CW) == 0 && r < nr) out(r, p);
     const double xr = r < nr ? x[r] : 0.0;
 #pragma unroll
@@ -157,7 +186,7 @@ template <int C, int CW>
 __device__ __forceinline__ void colsum_publish(double (&acc)[C], double* part, int pst, const Lanes& L) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const double s = xor_sum(acc[c], CW, 64);
+    const double s = lane_sum<CW, 64>(acc[c]);
     if (L.lane < CW) part[L.w * pst + frag_col<CW>(L, c)] = s;
   }
 }
@@ -167,11 +196,44 @@ __device__ __forceinline__ double colsum_total(const double* part, int pst, int 
   return s;
 }
 
-// Packed lower triangle (rows [0, n), row i holds i + 1 entries) into LDS as float64.
-template <typename T>
+// Packed lower triangle (rows [0, n), row i holds i + 1 entries) into LDS as float64 by NT
+// threads, CH loads per thread in flight per chunk (all issued before the first store).
+template <int NT, int CH, typename T>
 __device__ __forceinline__ void tri_to_lds(const T* __restrict__ P, int n, double* dst) {
   const int tot = n * (n + 1) / 2;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) dst[e] = (double)P[e];
+  for (int e0 = 0; e0 < tot; e0 += CH * NT) {
+    double v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = e0 + (int)threadIdx.x + c * NT;
+      v[c] = (double)P[(uint32_t)(e < tot ? e : tot - 1)];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = e0 + (int)threadIdx.x + c * NT;
+      if (e < tot) dst[e] = v[c];
+    }
+  }
+}
+// Loads per thread per chunk for a padded triangle of order NP (at most 8).
+__host__ __device__ constexpr int tri_chunk(int NP, int NT) {
+  return (NP * (NP + 1) / 2 + NT - 1) / NT < 8 ? (NP * (NP + 1) / 2 + NT - 1) / NT : 8;
+}
+// A packed lower triangle of order n as a dense fragment (zero above the diagonal and outside).
+template <int R, int C, int CW, typename T>
+__device__ __forceinline__ void frag_load_tri(Frag<R, C, CW>& f, const T* __restrict__ P, int n, const Lanes& L,
+                                              int W) {
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int r = frag_row<R, C, CW>(L, W, t);
+    const int rc = r < n ? r : n - 1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = frag_col<CW>(L, c);
+      const double e = (double)P[(uint32_t)(rc * (rc + 1) / 2 + (j <= rc ? j : rc))];
+      f.v[t][c] = keep_if(r < n && j <= r, e);
+    }
+  }
 }
 __device__ __forceinline__ int tri(int i) { return i * (i + 1) / 2; }
 
@@ -181,18 +243,25 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Triangular solves with L^R (packed in LDS, reciprocal diagonal dr): wavefront 0, lane j keeps
-// entry j.  TRANS: y = (L^R)^{-T} t, else y = (L^R)^{-1} t.  nu <= 64.
-template <bool TRANS>
+// Triangular solves with L^R (packed in LDS, reciprocal diagonal dr zero-padded to NUP):
+// wavefront 0, lane j keeps entry j.  TRANS: y = (L^R)^{-T} t, else y = (L^R)^{-1} t.  Unrolled
+// over the padded order, so the LDS reads of L^R do not wait on the substitution chain; steps
+// beyond nu leave zeros (their entries of t and dr are zero).
+template <bool TRANS, int NUP>
 __device__ __forceinline__ void lr_solve(const double* LR, const double* dr, int nu, const double* t, double* y) {
   if (threadIdx.x >= 64) return;
   const int j = threadIdx.x;
   double a = j < nu ? t[j] : 0.0;
-  for (int st = 0; st < nu; ++st) {
-    const int i = TRANS ? nu - 1 - st : st;
+  const int last = tri(nu) - 1;
+#pragma unroll
+  for (int st = 0; st < NUP; ++st) {
+    const int i = TRANS ? NUP - 1 - st : st;
+    const bool use = TRANS ? j < i : (j > i && j < nu);
+    const int e = TRANS ? tri(i) + j : tri(j) + i;
+    const double l = LR[e < last ? e : last];
     const double yi = readlane_d(a, i) * dr[i];
     if (j == 0) y[i] = yi;
-    if (TRANS ? j < i : (j > i && j < nu)) a = fma(-(TRANS ? LR[tri(i) + j] : LR[tri(j) + i]), yi, a);
+    if (use && i < nu) a = fma(-l, yi, a);
   }
 }
 
@@ -217,9 +286,9 @@ __device__ __forceinline__ void each_instance(int batch, const int32_t* order, i
 // LDS of the kernel for the padded sizes (doubles): vectors that live across stages, then the
 // per-stage staging area (triangles, column partials, block maxima).  The checkpointed kernels
 // overlay the staging area with the factor-sweep scratch of the segment recomputation.
-__host__ __device__ constexpr int tsolve_vec_doubles(int NXP, int NUP) { return 14 * NXP + 8 * NUP; }
+__host__ __device__ constexpr int tsolve_vec_doubles(int NXP, int NUP) { return 14 * NXP + 7 * NUP; }
 __host__ __device__ constexpr int tsolve_stage_doubles(int W, int NXP, int NUP) {
-  return NXP * (NXP + 1) / 2 + NUP * (NUP + 1) / 2 + W * (NXP + NUP) + 2 * W;
+  return (NXP <= 64 ? 0 : NXP * (NXP + 1) / 2) + NUP * (NUP + 1) / 2 + W * (NXP + NUP) + 2 * W;
 }
 __host__ __device__ constexpr int tsolve_lds_doubles(int W, int NXP, int NUP) {
   return tsolve_vec_doubles(NXP, NUP) + tsolve_stage_doubles(W, NXP, NUP);
@@ -259,12 +328,13 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
   double* au = ut + NUP;                    // residual accumulator (nu rows)
   double* s0 = au + NUP;                    // S x_init
   double* dr = s0 + NUP;                    // 1 / diag L^R_k
-  double* rv = dr + NUP;                    // correction right-hand side r
-  double* yb = rv + NUP;                    // rbar2
+  double* yb = dr + NUP;                    // rbar2
+  // L^Q_{k+1} as a register fragment up to NXP = 64 (beyond, through LDS)
+  constexpr bool LQREG = NXP <= 64;
   // LDS: per-stage staging
   double* stg = sm + tsolve_vec_doubles(NXP, NUP);
-  double* LQ = stg;                         // packed L^Q_{k+1}
-  double* LR = LQ + NXP * (NXP + 1) / 2;    // packed L^R_k
+  double* LQ = stg;                         // packed L^Q_{k+1} (NXP > 64)
+  double* LR = LQ + (LQREG ? 0 : NXP * (NXP + 1) / 2);  // packed L^R_k
   double* px = LR + NUP * (NUP + 1) / 2;    // column partials, nx-wide  [W][NXP]
   double* pu = px + W * NXP;                //                   nu-wide  [W][NUP]
   double* red = pu + W * NUP;               // [2 W] wavefront maxima
@@ -323,22 +393,59 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
   double* rhu = rb2 + v2_rhou(N, nx, nu);   // correction right-hand side r = -rho_u
   double* rhx = rb2 + v2_rhox(N, nx, nu);   // correction right-hand side q = -rho_x (k = 1..N)
   // right-hand side of the system being solved: (r, q, f, x_init), adjoint (-gu, -gx, 0, 0)
+  // (the stage loops read them unconditionally from clamped indices, sign and presence at use)
+  const double* r_src = adj ? gu : r;
+  const double* q_src = adj ? gx - nx : q;  // row k of the adjoint's q is gx row k - 1
+  const double* f_src = (!adj && f) ? f : q;
+  const double rhs_sign = adj ? -1.0 : 1.0;
+  const bool has_f = !adj && f;
   auto rhs_r = [&](int k, int i) { return adj ? -gu[(int64_t)k * nu + i] : r[(int64_t)k * nu + i]; };
   auto rhs_q = [&](int k, int i) { return adj ? -gx[(int64_t)(k - 1) * nx + i] : q[(int64_t)k * nx + i]; };
   auto rhs_f = [&](int k, int i) { return (!adj && f) ? f[(int64_t)k * nx + i] : 0.0; };
   auto rhs_x0 = [&](int i) { return adj ? 0.0 : x0[i]; };
 
+  // products with the packed triangle LQ in LDS (the path beyond NXP = 64), groups of XW lanes
+  // per column / row: out[j] = sum_{i >= j} LQ[i][j] x[i], then emit(i, sum_{j <= i} LQ[i][j] y[j])
+  auto tri_cols_lds = [&](const double* T, const double* x, int n, double* out, const Lanes& L) {
+    const int g = S::XW, sub = L.lane % g, per = nt / g;
+    for (int j0 = 0; j0 < n; j0 += per) {
+      const int j = j0 + tid / g;
+      double v = 0.0;
+      if (j < n)
+        for (int i = j + sub; i < n; i += g) v = fma(T[tri(i) + j], x[i], v);
+      v = lane_sum<1, S::XW>(v);
+      if (sub == 0 && j < n) out[j] = v;
+    }
+  };
+  auto tri_rows_lds = [&](const double* T, const double* y, int n, const Lanes& L, auto&& emit) {
+    const int g = S::XW, sub = L.lane % g, per = nt / g;
+    for (int i0 = 0; i0 < n; i0 += per) {
+      const int i = i0 + tid / g;
+      double v = 0.0;
+      if (i < n)
+        for (int j = sub; j <= i; j += g) v = fma(T[tri(i) + j], y[j], v);
+      v = lane_sum<1, S::XW>(v);
+      if (sub == 0 && i < n) emit(i, v);
+    }
+  };
+
   // zero padding of every LDS vector
-  for (int i = tid; i < 14 * NXP + 8 * NUP; i += nt) xc[i] = 0.0;
+  for (int i = tid; i < tsolve_vec_doubles(NXP, NUP); i += nt) xc[i] = 0.0;
   __syncthreads();
+
+  // Every global read of a stage is issued at the stage's start, before its first barrier, and
+  // consumed later, so that a stage waits for one memory round trip instead of one per use
+  // (barriers do not wait for outstanding global loads).  Thread t holds entry t of the stage's
+  // vectors (nt >= NXP >= nx, nu).
+  const bool rx = tid < nx, ru = tid < nu;
 
   // ---- forward rollout (mode 0: z = result, mode 1: z += correction) with the residual of the
   // updated iterate: correction right-hand sides for a following backward pass, returns rel_res.
   auto forward = [&](int mode, const double* rbv, const double* pvv) -> double {
     double mr = 0.0, mb = 0.0;
-    for (int i = tid; i < nx; i += nt) {
-      xc[i] = mode == 0 ? rhs_x0(i) : 0.0;
-      xt[i] = rhs_x0(i);
+    if (rx) {
+      xc[tid] = mode == 0 ? rhs_x0(tid) : 0.0;
+      xt[tid] = rhs_x0(tid);
     }
     __syncthreads();
     for (int k = 0; k < N; ++k) {
@@ -348,7 +455,25 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       const TF* blk1 = blk_of(k + 1);
       const double* Ak = A + (int64_t)k * nx * nx;
       const double* Bk = B + (int64_t)k * nx * nu;
-      // stage data into registers (the residual's Q, R, S too) and the triangles into LDS
+      const double* Qk = Q + (int64_t)k * nx * nx;
+      // ---- reads of the stage: Q_k first (its products with the known x_k come first), then the
+      // vectors, the other stage matrices into registers and the triangles into LDS
+      Frag<(NXP <= 64 ? S::RXX : 1), S::XC, S::XW> fQ;
+      if constexpr (NXP <= 64) {
+        if (k > 0) frag_load(fQ, Qk, nx, nx, nx, L, W);
+      }
+      // vectors: unconditional loads from clamped indices (entries past nx / nu are never used)
+      const int iu = ru ? tid : nu - 1, ix = rx ? tid : nx - 1;
+      const double v_rb = rbv[(int64_t)k * nu + iu];
+      const double v_dr = (double)blk[off_dR(nx, nu) + iu];
+      const double v_U0 = U[(int64_t)k * nu + iu];
+      const double v_r = rhs_sign * r_src[(int64_t)k * nu + iu];
+      const double v_f = keep_if(has_f, f_src[(int64_t)k * nx + ix]);
+      const double v_fl0 = flam[(int64_t)k * nx + ix];
+      const double v_X0 = X[(int64_t)k * nx + ix];
+      const double v_LM0 = LM[(int64_t)k * nx + ix];
+      const double v_p = pvv[(int64_t)(k + 1) * nx + ix];
+      const double v_q = rhs_sign * q_src[(int64_t)(k > 0 ? k : 1) * nx + ix];
       Frag<S::RXU, 1, S::UW> fLS, fB;
       Frag<S::RXX, S::XC, S::XW> fA;
       Frag<S::RUU, 1, S::UW> fR;
@@ -358,11 +483,23 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       frag_load(fB, Bk, nx, nu, nu, L, W);
       frag_load(fR, R + (int64_t)k * nu * nu, nu, nu, nu, L, W);
       if (Sm) frag_load(fS, Sm + (int64_t)k * nu * nx, nu, nx, nx, L, W);
-      tri_to_lds(blk, nu, LR);
-      tri_to_lds(blk1 + off_LQ(nx, nu), nx, LQ);
-      for (int j = tid; j < nu; j += nt) {
-        dr[j] = (double)blk[off_dR(nx, nu) + j];
-        us[j] = rbv[(int64_t)k * nu + j];
+      tri_to_lds<S::NT, tri_chunk(NUP, S::NT)>(blk, nu, LR);
+      if constexpr (!LQREG) tri_to_lds<S::NT, tri_chunk(NXP, S::NT)>(blk1 + off_LQ(nx, nu), nx, LQ);
+      // Q_k x_k (rows, into xs) and Q_k^T x_k (columns, hq) of the total iterate, k >= 1
+      double hq[S::XC];
+#pragma unroll
+      for (int c = 0; c < S::XC; ++c) hq[c] = 0.0;
+      if (k > 0) {
+        if constexpr (NXP <= 64) {
+          frag_rows(fQ, xt, nx, L, W, [&](int i, double v) { xs[i] = v; });
+          frag_cols(fQ, xt, nx, hq, L, W);
+        } else {
+          stream_sq<S::RXX, S::XC, S::XW>(Qk, nx, xt, hq, L, W, [&](int i, double v) { xs[i] = v; });
+        }
+      }
+      if (ru) {
+        dr[tid] = v_dr;
+        us[tid] = v_rb;
       }
       // s = rbar_k + (L^S_k)^T x_k
       {
@@ -370,58 +507,62 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
         frag_cols(fLS, xc, nx, acc, L, W);
         colsum_publish<1, S::UW>(acc, pu, NUP, L);
       }
+      // L^Q_{k+1} into registers (L^S_k is dead; the load completes behind the x-chain)
+      Frag<(LQREG ? S::RXX : 1), S::XC, S::XW> fLQ;
+      if constexpr (LQREG) frag_load_tri(fLQ, blk1 + off_LQ(nx, nu), nx, L, W);
       __syncthreads();
-      for (int j = tid; j < nu; j += nt) us[j] += colsum_total(pu, NUP, W, j);
+      if (ru) us[tid] += colsum_total(pu, NUP, W, tid);
       __syncthreads();
       // u_k = -(L^R_k)^{-T} s
-      lr_solve<true>(LR, dr, nu, us, uu);
+      lr_solve<true, NUP>(LR, dr, nu, us, uu);
       __syncthreads();
-      for (int j = tid; j < nu; j += nt) {
-        const double du = -uu[j];
-        uu[j] = du;
-        const double tot = mode == 0 ? du : U[(int64_t)k * nu + j] + du;
-        ut[j] = tot;
-        U[(int64_t)k * nu + j] = tot;
+      if (ru) {
+        const double du = -uu[tid];
+        uu[tid] = du;
+        const double tot = mode == 0 ? du : v_U0 + du;
+        ut[tid] = tot;
+        U[(int64_t)k * nu + tid] = tot;
       }
-      for (int i = tid; i < nx; i += nt) xn[i] = mode == 0 ? rhs_f(k, i) : flam[(int64_t)k * nx + i];
+      if (rx) xn[tid] = mode == 0 ? v_f : v_fl0;
       __syncthreads();
       // x_{k+1} = A x_k + B u_k + f_k (chain); A x_k + B u_k of the total iterate (residual)
-      frag_rows(fA, xc, nx, L, W, [&](int i, double s) { xn[i] += s; });
-      if (mode != 0) frag_rows(fA, xt, nx, L, W, [&](int i, double s) { al[i] = s; });
-      if (k == 0) frag_rows(fA, xt, nx, L, W, [&](int i, double s) { a0[i] = s; });
+      frag_rows(fA, xc, nx, L, W, [&](int i, double v) { xn[i] += v; });
+      if (mode != 0) frag_rows(fA, xt, nx, L, W, [&](int i, double v) { al[i] = v; });
+      if (k == 0) frag_rows(fA, xt, nx, L, W, [&](int i, double v) { a0[i] = v; });
       __syncthreads();
-      frag_rows(fB, uu, nx, L, W, [&](int i, double s) { xn[i] += s; });
+      frag_rows(fB, uu, nx, L, W, [&](int i, double v) { xn[i] += v; });
       __syncthreads();
-      if (mode != 0) frag_rows(fB, ut, nx, L, W, [&](int i, double s) { al[i] += s; });
-      for (int i = tid; i < nx; i += nt) {
-        const double tot = mode == 0 ? xn[i] : X[(int64_t)k * nx + i] + xn[i];
-        xt1[i] = tot;
-        X[(int64_t)k * nx + i] = tot;
+      if (mode != 0) frag_rows(fB, ut, nx, L, W, [&](int i, double v) { al[i] += v; });
+      if (rx) {
+        const double tot = mode == 0 ? xn[tid] : v_X0 + xn[tid];
+        xt1[tid] = tot;
+        X[(int64_t)k * nx + tid] = tot;
       }
       __syncthreads();
       // lam_k = L^Q_{k+1} (L^Q_{k+1})^T x_{k+1} + p_{k+1}
-      for (int j = tid; j < nx; j += nt) {
-        double s = 0.0;
-        for (int i = j; i < nx; ++i) s = fma(LQ[tri(i) + j], xn[i], s);
-        ct[j] = s;
+      if constexpr (LQREG) {
+        {
+          double cq[S::XC];
+#pragma unroll
+          for (int c = 0; c < S::XC; ++c) cq[c] = 0.0;
+          frag_cols(fLQ, xn, nx, cq, L, W);
+          colsum_publish<S::XC, S::XW>(cq, px, NXP, L);
+        }
+        __syncthreads();
+        if (rx) ct[tid] = colsum_total(px, NXP, W, tid);
+        __syncthreads();
+        frag_rows(fLQ, ct, nx, L, W, [&](int i, double v) { lt[i] = v; });
+      } else {
+        tri_cols_lds(LQ, xn, nx, ct, L);
+        __syncthreads();
+        tri_rows_lds(LQ, ct, nx, L, [&](int i, double v) { lt[i] = v; });
       }
       __syncthreads();
-      {
-        // row sums over the triangle with groups of XW lanes per row
-        const int g = S::XW, sub = L.lane % g, per = nt / g;
-        for (int i0 = 0; i0 < nx; i0 += per) {
-          const int i = i0 + tid / g;
-          double s = 0.0;
-          if (i < nx)
-            for (int j = sub; j <= i; j += g) s = fma(LQ[tri(i) + j], ct[j], s);
-          s = xor_sum(s, 1, g);
-          if (sub == 0 && i < nx) {
-            const double l = pvv[(int64_t)(k + 1) * nx + i] + s;
-            const double tot = mode == 0 ? l : LM[(int64_t)k * nx + i] + l;
-            lt[i] = tot;
-            LM[(int64_t)k * nx + i] = tot;
-          }
-        }
+      if (rx) {
+        const double l = v_p + lt[tid];
+        const double tot = mode == 0 ? l : v_LM0 + l;
+        lt[tid] = tot;
+        LM[(int64_t)k * nx + tid] = tot;
       }
       __syncthreads();
       // residual rows of stage k (total iterate)
@@ -433,12 +574,6 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
         frag_cols(fA, lt, nx, cx, L, W);      // A^T lam_k
         frag_cols(fB, lt, nx, cu, L, W);      // B^T lam_k
         if (k > 0) {
-          double hq[S::XC];
-#pragma unroll
-          for (int c = 0; c < S::XC; ++c) hq[c] = 0.0;
-          // Q_k x_k (rows, into xs) and Q_k^T x_k (columns), streamed
-          stream_sq<S::RXX, S::XC, S::XW>(Q + (int64_t)k * nx * nx, nx, xt, hq, L, W,
-                                          [&](int i, double v) { xs[i] = v; });
 #pragma unroll
           for (int c = 0; c < S::XC; ++c) cx[c] = fma(0.5, hq[c], cx[c]);
         }
@@ -450,40 +585,37 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
         colsum_publish<1, S::UW>(cu, pu, NUP, L);
       }
       __syncthreads();
-      for (int i = tid; i < nx; i += nt) ax[i] = colsum_total(px, NXP, W, i) + (k > 0 ? 0.5 * xs[i] : 0.0);
-      for (int j = tid; j < nu; j += nt) au[j] = colsum_total(pu, NUP, W, j);
+      if (rx) ax[tid] = colsum_total(px, NXP, W, tid) + (k > 0 ? 0.5 * xs[tid] : 0.0);
+      if (ru) au[tid] = colsum_total(pu, NUP, W, tid);
       __syncthreads();
-      frag_rows(fR, ut, nu, L, W, [&](int i, double s) { au[i] = fma(0.5, s, au[i]); });
+      frag_rows(fR, ut, nu, L, W, [&](int i, double v) { au[i] = fma(0.5, v, au[i]); });
       __syncthreads();
-      if (Sm) frag_rows(fS, xt, nu, L, W, [&](int i, double s) { au[i] += s; if (k == 0) s0[i] = s; });
+      if (Sm) frag_rows(fS, xt, nu, L, W, [&](int i, double v) { au[i] += v; if (k == 0) s0[i] = v; });
       __syncthreads();
-      for (int j = tid; j < nu; j += nt) {
-        const double ri = rhs_r(k, j);
-        const double rho = -ri - au[j];
+      if (ru) {
+        const double rho = -v_r - au[tid];
         mr = nan_max(mr, fabs(rho));
-        mb = nan_max(mb, fabs(ri + (k == 0 && Sm ? s0[j] : 0.0)));
-        rhu[(int64_t)k * nu + j] = -rho;
+        mb = nan_max(mb, fabs(v_r + (k == 0 && Sm ? s0[tid] : 0.0)));
+        rhu[(int64_t)k * nu + tid] = -rho;
       }
-      for (int i = tid; i < nx; i += nt) {
-        const double fi = rhs_f(k, i);
-        const double axu = mode == 0 ? xn[i] - (mode == 0 ? rhs_f(k, i) : 0.0) : al[i];
-        const double rho = -fi - (axu - xt1[i]);
+      if (rx) {
+        const double axu = mode == 0 ? xn[tid] - v_f : al[tid];
+        const double rho = -v_f - (axu - xt1[tid]);
         mr = nan_max(mr, fabs(rho));
-        mb = nan_max(mb, fabs(fi + (k == 0 ? a0[i] : 0.0)));
-        flam[(int64_t)k * nx + i] = -rho;
+        mb = nan_max(mb, fabs(v_f + (k == 0 ? a0[tid] : 0.0)));
+        flam[(int64_t)k * nx + tid] = -rho;
         if (k > 0) {
-          const double qi = rhs_q(k, i);
-          const double rho2 = -qi - (ax[i] - ltm[i]);
+          const double rho2 = -v_q - (ax[tid] - ltm[tid]);
           mr = nan_max(mr, fabs(rho2));
-          mb = nan_max(mb, fabs(qi));
-          rhx[(int64_t)k * nx + i] = -rho2;
+          mb = nan_max(mb, fabs(v_q));
+          rhx[(int64_t)k * nx + tid] = -rho2;
         }
       }
       __syncthreads();
-      for (int i = tid; i < nx; i += nt) {
-        xc[i] = xn[i];
-        xt[i] = xt1[i];
-        ltm[i] = lt[i];
+      if (rx) {
+        xc[tid] = xn[tid];
+        xt[tid] = xt1[tid];
+        ltm[tid] = lt[tid];
       }
       __syncthreads();
     }
@@ -496,14 +628,14 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       stream_sq<S::RXX, S::XC, S::XW>(Q + (int64_t)N * nx * nx, nx, xt, cx, L, W, [&](int i, double v) { xs[i] = v; });
       colsum_publish<S::XC, S::XW>(cx, px, NXP, L);
       __syncthreads();
-      for (int i = tid; i < nx; i += nt) ax[i] = 0.5 * (colsum_total(px, NXP, W, i) + xs[i]);
+      if (rx) ax[tid] = 0.5 * (colsum_total(px, NXP, W, tid) + xs[tid]);
       __syncthreads();
-      for (int i = tid; i < nx; i += nt) {
-        const double qi = rhs_q(N, i);
-        const double rho = -qi - (ax[i] - ltm[i]);
+      if (rx) {
+        const double qi = rhs_q(N, tid);
+        const double rho = -qi - (ax[tid] - ltm[tid]);
         mr = nan_max(mr, fabs(rho));
         mb = nan_max(mb, fabs(qi));
-        rhx[(int64_t)N * nx + i] = -rho;
+        rhx[(int64_t)N * nx + tid] = -rho;
       }
     }
     // workgroup maxima: within each wavefront, then over the W wavefront values
@@ -528,12 +660,12 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
 
   // ---- backward sweep of the stored correction right-hand side (r, q, f) = (rhu, rhx, flam),
   // x_init = 0: rbar2_k = (L^R_k)^{-1}(r_k + B_k^T w), p2_k = q_k + A_k^T w - L^S_k rbar2_k,
-  // w = L^Q_{k+1} (L^Q_{k+1})^T f_k + p2_{k+1}, p2_N = q_N.
+  // w = L^Q_{k+1} (L^Q_{k+1})^T f_k + p2_{k+1}, p2_N = q_N.  Reads issued at the stage start.
   auto backward = [&]() {
-    for (int i = tid; i < nx; i += nt) {
-      const double v = rhx[(int64_t)N * nx + i];
-      pn[i] = v;
-      p2[(int64_t)N * nx + i] = v;
+    if (rx) {
+      const double v = rhx[(int64_t)N * nx + tid];
+      pn[tid] = v;
+      p2[(int64_t)N * nx + tid] = v;
     }
     __syncthreads();
     for (int k = N - 1; k >= 0; --k) {
@@ -541,36 +673,40 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       const Lanes L = lanes_now();
       const TF* blk = blk_of(k);
       const TF* blk1 = blk_of(k + 1);
+      const int iu = ru ? tid : nu - 1, ix = rx ? tid : nx - 1;
+      const double v_fl = flam[(int64_t)k * nx + ix];
+      const double v_q = keep_if(k > 0, rhx[(int64_t)k * nx + ix]);
+      const double v_dr = (double)blk[off_dR(nx, nu) + iu];
+      const double v_rv = rhu[(int64_t)k * nu + iu];
       Frag<S::RXU, 1, S::UW> fLS, fB;
       Frag<S::RXX, S::XC, S::XW> fA;
       frag_load(fB, B + (int64_t)k * nx * nu, nx, nu, nu, L, W);
       frag_load(fA, A + (int64_t)k * nx * nx, nx, nx, nx, L, W);
       frag_load(fLS, blk + off_LS(nx, nu), nx, nu, nu, L, W);
-      tri_to_lds(blk1 + off_LQ(nx, nu), nx, LQ);
-      tri_to_lds(blk, nu, LR);
-      for (int i = tid; i < nx; i += nt) fl[i] = flam[(int64_t)k * nx + i];
-      for (int j = tid; j < nu; j += nt) {
-        dr[j] = (double)blk[off_dR(nx, nu) + j];
-        rv[j] = rhu[(int64_t)k * nu + j];
-      }
+      Frag<(LQREG ? S::RXX : 1), S::XC, S::XW> fLQ;
+      if constexpr (LQREG) frag_load_tri(fLQ, blk1 + off_LQ(nx, nu), nx, L, W);
+      else tri_to_lds<S::NT, tri_chunk(NXP, S::NT)>(blk1 + off_LQ(nx, nu), nx, LQ);
+      tri_to_lds<S::NT, tri_chunk(NUP, S::NT)>(blk, nu, LR);
+      if (rx) fl[tid] = v_fl;
+      if (ru) dr[tid] = v_dr;
       __syncthreads();
       // w = L^Q (L^Q^T f) + p2_{k+1}
-      for (int j = tid; j < nx; j += nt) {
-        double s = 0.0;
-        for (int i = j; i < nx; ++i) s = fma(LQ[tri(i) + j], fl[i], s);
-        xs[j] = s;
-      }
-      __syncthreads();
-      {
-        const int g = S::XW, sub = L.lane % g, per = nt / g;
-        for (int i0 = 0; i0 < nx; i0 += per) {
-          const int i = i0 + tid / g;
-          double s = 0.0;
-          if (i < nx)
-            for (int j = sub; j <= i; j += g) s = fma(LQ[tri(i) + j], xs[j], s);
-          s = xor_sum(s, 1, g);
-          if (sub == 0 && i < nx) ct[i] = pn[i] + s;
+      if constexpr (LQREG) {
+        {
+          double cq[S::XC];
+#pragma unroll
+          for (int c = 0; c < S::XC; ++c) cq[c] = 0.0;
+          frag_cols(fLQ, fl, nx, cq, L, W);
+          colsum_publish<S::XC, S::XW>(cq, px, NXP, L);
         }
+        __syncthreads();
+        if (rx) xs[tid] = colsum_total(px, NXP, W, tid);
+        __syncthreads();
+        frag_rows(fLQ, xs, nx, L, W, [&](int i, double v) { ct[i] = pn[i] + v; });
+      } else {
+        tri_cols_lds(LQ, fl, nx, xs, L);
+        __syncthreads();
+        tri_rows_lds(LQ, xs, nx, L, [&](int i, double v) { ct[i] = pn[i] + v; });
       }
       __syncthreads();
       // (rhat, qhat) = (r, q) + [B A]^T w
@@ -585,19 +721,19 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
         colsum_publish<1, S::UW>(cu, pu, NUP, L);
       }
       __syncthreads();
-      for (int j = tid; j < nu; j += nt) us[j] = rv[j] + colsum_total(pu, NUP, W, j);
-      for (int i = tid; i < nx; i += nt) qv[i] = (k > 0 ? rhx[(int64_t)k * nx + i] : 0.0) + colsum_total(px, NXP, W, i);
+      if (ru) us[tid] = v_rv + colsum_total(pu, NUP, W, tid);
+      if (rx) qv[tid] = v_q + colsum_total(px, NXP, W, tid);
       __syncthreads();
       // rbar2 = (L^R)^{-1} rhat
-      lr_solve<false>(LR, dr, nu, us, yb);
+      lr_solve<false, NUP>(LR, dr, nu, us, yb);
       __syncthreads();
-      for (int j = tid; j < nu; j += nt) rb2[(int64_t)k * nu + j] = yb[j];
+      if (ru) rb2[(int64_t)k * nu + tid] = yb[tid];
       // p2_k = qhat - L^S rbar2
       if (k > 0) {
-        frag_rows(fLS, yb, nx, L, W, [&](int i, double s) {
-          const double v = qv[i] - s;
-          pn[i] = v;
-          p2[(int64_t)k * nx + i] = v;
+        frag_rows(fLS, yb, nx, L, W, [&](int i, double v) {
+          const double pk = qv[i] - v;
+          pn[i] = pk;
+          p2[(int64_t)k * nx + i] = pk;
         });
       }
       __syncthreads();

@@ -684,13 +684,20 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     // stage N: Q_N x_N - lam_{N-1} = -q_N
     const int64_t bb = L.bb;
     const double* QN = s.d.Q + (bb * (N + 1) + N) * NX * NX;
+    // row and column of Q_N and q_N loaded before any use, so that they arrive together
+    double qr[NX], qc[NX];
+#pragma unroll
+    for (int n = 0; n < NX; ++n) {
+      qr[n] = QN[mi * NX + n];
+      qc[n] = QN[n * NX + mi];
+    }
+    const double qv = s.d.q[(bb * (N + 1) + N) * NX + mi];
     double ax = -lkm;
 #pragma unroll
     for (int n = 0; n < NX; ++n) {
       const double xb = bc(xk, NU + n);
-      ax = fma(0.5 * (QN[mi * NX + n] + QN[n * NX + mi]), xb, ax);
+      ax = fma(0.5 * (qr[n] + qc[n]), xb, ax);
     }
-    const double qv = s.d.q[(bb * (N + 1) + N) * NX + mi];
     const double rhox = -qv - ax;
     if (xl) {
       mr = nan_max(mr, fabs(rhox));
@@ -732,7 +739,9 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
     fn.load(s.F, fistr, L, batch, N - 2);
     dn.load(s.d, N, L, batch, N - 2, false);
   }
-  double rho = isu ? s.rhou[(int64_t)(N - 1) * NU + ic] : s.rhox[(int64_t)(N - 1) * NX + mi];
+  // (the lane's residual entry is read through a selected address: selecting between two loaded
+  // values would wait for both right after they are issued)
+  double rho = *(isu ? s.rhou + (int64_t)(N - 1) * NU + ic : s.rhox + (int64_t)(N - 1) * NX + mi);
   double fl = s.flam[(int64_t)(N - 1) * NX + mi];
   for (int k = N - 1; k >= 0; --k) {
     if (k < N - 1) {
@@ -746,8 +755,7 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
     }
     double rho_n = 0.0, fl_n = 0.0;
     if (k > 0) {
-      const double ru = s.rhou[(int64_t)(k - 1) * NU + ic], rx = s.rhox[(int64_t)(k - 1) * NX + mi];
-      rho_n = isu ? ru : rx;
+      rho_n = *(isu ? s.rhou + (int64_t)(k - 1) * NU + ic : s.rhox + (int64_t)(k - 1) * NX + mi);
       fl_n = s.flam[(int64_t)(k - 1) * NX + mi];
     }
     constexpr int RSP = SH::RSP;

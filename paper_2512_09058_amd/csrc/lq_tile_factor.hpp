@@ -68,6 +68,13 @@ __device__ __forceinline__ double bc(double v, int k) {
   return __longlong_as_double(x);
 }
 
+// Value of lane l (wave-uniform l) for every lane.
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __hiloint2double(hi, lo);
+}
+
 // Order the LDS accesses of one wavefront (its DS operations complete in issue order).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
@@ -173,17 +180,22 @@ __device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c) {
   return ok ? 0 : (fin ? 1 : 2);
 }
 
-// Column c of X = L^{-1} for the lower-triangular 16x16 L in LDS (row-major, leading dimension
-// ld) with reciprocal diagonal di: forward substitution, entirely within the lane (the entries of
-// L are the same for every lane).  x[r] = X[r][c].
-__device__ __forceinline__ void inv16_col(double (&x)[16], const double* Lt, int ld, const double* di, int c) {
-#pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = r == c ? 1.0 : 0.0;
+// Row c of X = L^{-1} in lane c of each 16-lane row, from L held one row per lane (h[k] = L[c][k]
+// for k <= c, as chol16 leaves it) and dinv = 1 / L[c][c]:
+//   X[c] = dinv e_c - sum_{k<c} (dinv L[c][k]) X[k],
+// with the rows X[k] taken in order k = 0, 1, ... by row broadcasts (row k is final once the steps
+// before it are done).  Registers and DPP only.
+__device__ __forceinline__ void inv16_rows(double (&x)[16], const double (&h)[16], double dinv, int c) {
+  double m[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    x[k] *= di[k];
+    m[k] = k < c ? dinv * h[k] : 0.0;
+    x[k] = k == c ? dinv : 0.0;
+  }
 #pragma unroll
-    for (int r = k + 1; r < 16; ++r) x[r] = fma(-Lt[r * ld + k], x[k], x[r]);
+  for (int k = 0; k < 15; ++k) {
+#pragma unroll
+    for (int q = 0; q <= k; ++q) x[q] = fma(-m[k], bc(x[q], k), x[q]);
   }
 }
 
@@ -467,26 +479,20 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           for (int q = 0; q < 16; ++q) h[q] = SC[c * LD + q];
           const int bad = chol16(h, dinv, c);
           if (bad && lane == 0 && s_info == 0) s_info = bad == 2 ? LQ_INFO_NONFINITE : k + 1;
-          wave_sync();
-          // L_jj row-major into the scratch tile (for the inverse), U(j, j) = L_jj^T into its
-          // panel / the L^Q tiles
+          // U(j, j) = L_jj^T into its panel / the L^Q tiles
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) {
             const int q = 4 * g + qq;
             const double l = q <= c ? pick4(h, g, qq) : 0.0;
-            SC[c * LD + q] = l;
             if (j < TU) upan(j, j)[q * LD + c] = l;
             else lqb(j - TU, j - TU)[q * LQ + c] = (TF)l;
           }
           if (g == 0) dv[16 * j + c] = dinv;
-          wave_sync();
-        }
-        {
-          // X = L_jj^{-1}; DI holds X^T row-major (row c = column c of X)
+          // X = L_jj^{-1}; DI holds X^T row-major (row q = column q of X: DI[q][c] = X[c][q])
           double x[16];
-          inv16_col(x, SC, LD, dv + 16 * j, c);
+          inv16_rows(x, h, dinv, c);
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq) DI[c * LD + 4 * g + qq] = pick4(x, g, qq);
+          for (int qq = 0; qq < 4; ++qq) DI[(4 * g + qq) * LD + c] = pick4(x, g, qq);
         }
         // column j is complete: none of its tiles is read again, and redefining them here lets
         // the diagonal step reuse their registers
@@ -531,7 +537,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           for (int jj = 0; jj < i0; ++jj)
             if (i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * rb[jj];
           for (int jj = i0; jj < nu && jj < i0 + 64; ++jj) {
-            const double y = __shfl(acc * di, jj - i0);
+            const double y = lane_bcast(acc * di, jj - i0);
             if (i > jj && i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * y;
           }
           if (i < nu) {

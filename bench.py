@@ -200,14 +200,23 @@ def _gen_worker(args):
     return i, {k: getattr(p, k) for k in ("A", "B", "Q", "R", "q", "r", "x0")}
 
 
-def _gen_uniform(cfg, count, workers=16):
+def _gen_uniform(cfg, count, workers=16, distinct=0):
     """`count` instances of workload `cfg`, generated in parallel processes, as the packed device
-    arrays of the library (uniform batch: instance blocks back to back)."""
+    arrays of the library (uniform batch: instance blocks back to back).  distinct > 0: only that
+    many instances, generated in this process and repeated cyclically (same shapes and value
+    distributions; for short profiled runs)."""
     import torch
     import synth
-    print(f"[bench] generating {count} instances in {min(workers, count)} processes", file=sys.stderr, flush=True)
     first = synth.make_instance(cfg, 0)
     host = {k: np.empty((count,) + getattr(first, k).shape) for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+    if distinct > 0:
+        print(f"[bench] generating {distinct} distinct instances, repeated to {count}", file=sys.stderr, flush=True)
+        insts = [first] + [synth.make_instance(cfg, i) for i in range(1, min(distinct, count))]
+        for i in range(count):
+            for k in host:
+                host[k][i] = getattr(insts[i % len(insts)], k)
+        return {k: torch.from_numpy(v.reshape(-1)).to("cuda") for k, v in host.items()}
+    print(f"[bench] generating {count} instances in {min(workers, count)} processes", file=sys.stderr, flush=True)
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[v] = "1"  # one BLAS thread per worker process
     ctx = mp.get_context("spawn")
@@ -279,7 +288,7 @@ def bench_large(args):
     from oracle import riccati
     b, Nn, nx, nu = 64, 1000, 128, 32
     t0 = time.perf_counter()
-    data = _gen_uniform(4, b)
+    data = _gen_uniform(4, b, distinct=args.distinct)
     torch.cuda.synchronize()
     print(f"[bench] generated and uploaded the large workload in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
@@ -363,6 +372,7 @@ def bench_adjoint(args):
         info = torch.zeros(b, dtype=torch.int32, device="cuda")
         rel = torch.zeros(b, dtype=torch.float64, device="cuda")
         relb = torch.zeros(b, dtype=torch.float64, device="cuda")
+        its = torch.zeros(b, dtype=torch.int32, device="cuda")
         x, u, lam = plan.empty_outputs()
         g = {k: torch.empty(plan.totals[k], dtype=torch.float64, device="cuda")
              for k in ("A", "B", "Q", "R", "q", "r", "x0")}
@@ -373,7 +383,7 @@ def bench_adjoint(args):
             e[0].record(stream)
             L.factor(plan, data, ws, info, stream=stream)
             e[1].record(stream)
-            L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=mi, check_res=True, stream=stream)
+            L.solve(plan, data, ws, x, u, lam, rel, its, info, tol=TOL, max_it=mi, check_res=True, stream=stream)
             e[2].record(stream)
             L.solve_backward(plan, data, ws, x, u, lam, x, u, g, relb, None, info, tol=TOL, max_it=mi,
                              stream=stream)
@@ -386,7 +396,14 @@ def bench_adjoint(args):
         res[key] = {"value": b / (sum(t) * 1e-3), "ms_per_step": sum(t), "ms_factor": t[0], "ms_solve": t[1],
                     "ms_backward": t[2], "max_rel_res": float(rel.max().item()),
                     "max_rel_res_adjoint": float(relb.max().item()), "info_ok": bool((info == 0).all().item()),
-                    "variant": plan.variant, "workspace_bytes": plan.workspace_bytes}
+                    "variant": plan.variant, "workspace_bytes": plan.workspace_bytes,
+                    "iters_max": int(its.max().item())}
+        fb = 8 if mode == "f64" else 4
+        sbytes = algorithmic_bytes_solve(Nn, nx, nu, fb, its.cpu().numpy())
+        res[key]["solve_roofline"] = {"bound": "hbm", "kernel": "solve", "achieved": sbytes / (t[1] * 1e-3) / 1e9,
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": sbytes / (t[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                                      "algorithmic_bytes_per_launch": sbytes, "ms_per_launch": t[1]}
         print(f"[bench] adjoint {key}: factor {t[0]:.2f} ms, solve {t[1]:.2f} ms, backward {t[2]:.2f} ms, "
               f"rel {rel.max().item():.1e} / {relb.max().item():.1e}", file=sys.stderr, flush=True)
     m = res["mixed_f32_ckpt10"]
@@ -397,7 +414,7 @@ def bench_adjoint(args):
            "data": "synthetic (seeded generators of the workload)",
            "config": {"workload": "batch 1024 LQ problems, N=100, nx=32, nu=8, forward + adjoint", "batch": b,
                       "N": Nn, "nx": nx, "nu": nu, "tol": TOL, "ckpt_stride": 10},
-           "paths": res, "roofline": None,
+           "paths": res, "roofline": m["solve_roofline"],
            "cpu_baseline": None if args.no_cpu else _cpu_uniform(5, 1, 16, True,
                                                                  "dense KKT solve + dense adjoint solve")}
     print(json.dumps(out))
@@ -411,6 +428,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-it", type=int, default=10)
+    ap.add_argument("--distinct", type=int, default=0,
+                    help="large / adjoint workloads: generate only this many distinct instances and repeat them "
+                         "(0: all distinct)")
     ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024"], default="batch4096",
                     help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
                          "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")

@@ -357,7 +357,8 @@ def bench_adjoint(args):
     """The adjoint workload: 1024 instances, N = 100, nx = 32, nu = 8 (generators of the batch-4096
     workload); one step = factor + solve + lq_solve_backward for the loss 1/2 sum(|x_k|^2 + |u_k|^2)
     (upstream gradients x, u), float32 products with float64 Cholesky and refinement, factors
-    checkpointed every 10 stages (the reported path); without checkpoints and in float64 beside it."""
+    checkpointed every 10 stages (the reported path); without checkpoints and in float64 (with and
+    without checkpoints) beside it."""
     import torch
     import synth
     import paper_2512_09058_amd as L
@@ -366,7 +367,7 @@ def bench_adjoint(args):
     data = L.pack(prob)
     Nn, nx, nu = prob.N, prob.nx, prob.nu
     res = {}
-    for mode, ckpt, mi in (("mixed_f32", 10, args.max_it), ("mixed_f32", 0, args.max_it), ("f64", 0, 0)):
+    for mode, ckpt, mi in (("mixed_f32", 10, args.max_it), ("mixed_f32", 0, args.max_it), ("f64", 10, 0), ("f64", 0, 0)):
         plan = L.Plan(Nn, nx, nu, batch=b, mode=mode, ckpt_stride=ckpt)
         ws = plan.workspace()
         info = torch.zeros(b, dtype=torch.int32, device="cuda")

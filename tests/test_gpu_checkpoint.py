@@ -174,3 +174,23 @@ def test_nonfinite_right_hand_side_reports_info():
             assert res["info"][1] == -1, (variant, ckpt, mode, res["info"])
             assert np.isnan(res["rel"][1]), (variant, ckpt, mode, res["rel"])
             assert res["info"][0] == 0 and res["info"][2] == 0, (variant, ckpt, mode, res["info"])
+
+
+@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 8)])
+def test_tile_checkpointed_ragged_batch(mode, max_it):
+    """A ragged checkpointed batch spanning both padded state sizes of the checkpointed tile solve
+    (nx 10..60, nu 3..40, N 6..31, stride 7; persistent grid): library residual, oracle residual and
+    forward error for every instance."""
+    import numpy as np_
+    rng = np_.random.default_rng(77)
+    insts = [synth.random_problem(900 + i, int(rng.integers(6, 32)), int(rng.integers(10, 61)),
+                                  int(rng.integers(3, 41))) for i in range(10)]
+    print(f"case: tile checkpointed ragged {mode}", flush=True)
+    plan = L.Plan([p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts], mode=mode, ckpt_stride=7)
+    assert plan.variant == "tile"
+    res = run(insts, mode, max_it=max_it, plan=plan)
+    assert np.all(res["info"] == 0) and res["rel"].max() <= 1e-10, (res["info"], res["rel"])
+    for i, p in enumerate(insts):
+        sol = instance_solution(res, i)
+        assert kkt.residual(p, *sol)[1] <= 1e-10, i
+        assert forward_error(sol, oracle_solution(p)) <= 1e-9, i

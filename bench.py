@@ -156,8 +156,8 @@ def bench_uneven(args):
     import synth
     import paper_2512_09058_amd as L
     from paper_2512_09058_amd import tune
-    from oracle import kkt
     insts = synth.make_ragged(2048)
+    sols = {}
     data = L.pack(insts)
     Ns, nxs, nus = [p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts]
     out = {"metric": "LQ KKT solves/s, uneven batch 2048 (nx 6..64, nu 2..16, N 10..200)", "unit": "solves/s",
@@ -179,18 +179,120 @@ def bench_uneven(args):
             g.replay()
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        # per-kernel launch times (events on the library's stream, outside the graph)
+        stream = torch.cuda.current_stream()
+        kt = []
+        for _ in range(3):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            L.factor(plan, data, ws, info, stream=stream)
+            e[1].record(stream)
+            L.solve(plan, data, ws, x, u, lam, rel, its, info, tol=TOL, max_it=max_it, check_res=True, stream=stream)
+            e[2].record(stream)
+            kt.append(e)
+        torch.cuda.synchronize()
+        tf = float(np.median([e[0].elapsed_time(e[1]) for e in kt]))
+        tsv = float(np.median([e[1].elapsed_time(e[2]) for e in kt]))
         relh = rel.cpu().numpy()
-        worst = max(kkt.residual(insts[i], L.unpack(plan, "x", x, i), L.unpack(plan, "u", u, i),
-                                 L.unpack(plan, "lam", lam, i))[1] for i in (0, 1023, 2047))
+        itsh = its.cpu().numpy()
+        sols[mode] = _host_solutions(plan, x, u, lam)
+        fb = 8 if mode == "f64" else 4
+        fbytes = sum(algorithmic_bytes_factor(1, p.N, p.nx, p.nu, fb) for p in insts)
+        sbytes = sum(algorithmic_bytes_solve(p.N, p.nx, p.nu, fb, [itsh[i]]) for i, p in enumerate(insts))
+        kern = {"factor": (tf, fbytes), "solve": (tsv, sbytes)}
+        dom = max(kern, key=lambda k_: kern[k_][0])
+        ach = kern[dom][1] / (kern[dom][0] * 1e-3) / 1e9
         out[mode] = {"value": 2048 / (ms * 1e-3), "ms_per_step": ms, "variant": choice["variant"],
                      "launch": choice["launch"],
-                     "max_rel_res": float(relh.max()), "iters_max": int(its.max().item()),
-                     "info_ok": bool((info == 0).all().item()), "oracle_rel_res_sampled": worst}
+                     "max_rel_res": float(relh.max()), "iters_max": int(itsh.max()),
+                     "info_ok": bool((info == 0).all().item()), "ms_factor": tf, "ms_solve": tsv,
+                     "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                                  "algorithmic_bytes_per_launch": kern[dom][1], "ms_per_launch": kern[dom][0]},
+                     "buckets": _bucket_report(insts, relh, itsh)}
         print(f"[bench] uneven {mode}: {ms:.2f} ms/step, variant {choice['variant']}, launch {choice['launch']}, "
               f"max rel_res {relh.max():.2e}",
               file=sys.stderr, flush=True)
+    # per nx bucket: deviation of the mixed path from the float64 GPU solution (every instance)
+    for lo, hi in NX_BUCKETS:
+        idx = [i for i, p in enumerate(insts) if lo <= p.nx <= hi]
+        dev = max(_fwd_err(sols["mixed_f32"][i], sols["f64"][i]) for i in idx)
+        out["mixed_f32"]["buckets"][f"nx {lo}-{hi}"]["max_fwd_err_vs_f64_gpu"] = dev
+        print(f"[bench] uneven bucket nx {lo}-{hi}: {len(idx)} instances, mixed vs f64 {dev:.1e}",
+              file=sys.stderr, flush=True)
     out["value"] = out["mixed_f32"]["value"]
+    out["roofline"] = out["mixed_f32"]["roofline"]
+    out["cpu_baseline"] = None if args.no_cpu else _cpu_uneven(insts, sols)
     print(json.dumps(out))
+
+
+NX_BUCKETS = ((6, 16), (17, 32), (33, 48), (49, 64))
+
+
+def _host_solutions(plan, x, u, lam):
+    """(x, u, lam) of every instance as host arrays (one copy of each output array)."""
+    out = []
+    arrs = {n: t.cpu().numpy() for n, t in (("x", x), ("u", u), ("lam", lam))}
+    for i in range(plan.batch):
+        N, nx, nu = int(plan.N[i]), int(plan.nx[i]), int(plan.nu[i])
+        blk = []
+        for n, d in (("x", nx), ("u", nu), ("lam", nx)):
+            o = int(plan.offsets[n][i])
+            blk.append(arrs[n][o:o + N * d].reshape(N, d))
+        out.append(tuple(blk))
+    return out
+
+
+def _fwd_err(sol, ref):
+    return float(max(np.abs(a - b).max() for a, b in zip(sol, ref)) / max(np.abs(b).max() for b in ref))
+
+
+def _uneven_oracle_worker(chunk):
+    from oracle import riccati
+    t0 = time.perf_counter()
+    for p in chunk:
+        riccati.solve(p)
+    return time.perf_counter() - t0
+
+
+def _cpu_uneven(insts, sols, per_bucket=None, workers=16):
+    """The CPU leg of the uneven workload: the oracle's textbook Riccati route timed on the batch
+    (or on per_bucket instances of each nx bucket; 16 processes, one BLAS thread each); then, per
+    bucket, the oracle's residual of the GPU solutions and their forward error against the
+    oracle's solution on three sampled instances."""
+    from oracle import kkt, riccati
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    sample = []
+    for lo, hi in NX_BUCKETS:
+        sample += [p for p in insts if lo <= p.nx <= hi][:per_bucket]
+    chunks = [sample[w::workers] for w in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        times = pool.map(_uneven_oracle_worker, chunks)
+    t = max(times)
+    check = {}
+    for lo, hi in NX_BUCKETS:
+        idx = [i for i, p in enumerate(insts) if lo <= p.nx <= hi]
+        pick = idx[:: max(1, len(idx) // 3)][:3]
+        ref = {i: riccati.solve(insts[i]) for i in pick}
+        check[f"nx {lo}-{hi}"] = {
+            mode: {"oracle_rel_res": max(kkt.residual(insts[i], *sols[mode][i])[1] for i in pick),
+                   "fwd_err_vs_oracle": max(_fwd_err(sols[mode][i], ref[i]) for i in pick)}
+            for mode in sols}
+    return {"value": len(sample) / t, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(sample)} instances ({per_bucket or 'all'} per nx bucket), textbook Riccati route (numpy float64, "
+                      f"1 BLAS thread per process), {workers} processes, slowest {t:.1f} s",
+            "gpu_vs_oracle_sampled": check}
+
+
+def _bucket_report(insts, rel, its):
+    """Per nx bucket: instance count, largest library rel_res, refinement iterations."""
+    rep = {}
+    for lo, hi in NX_BUCKETS:
+        idx = [i for i, p in enumerate(insts) if lo <= p.nx <= hi]
+        rep[f"nx {lo}-{hi}"] = {"instances": len(idx), "max_rel_res": float(rel[idx].max()),
+                                "iters_max": int(its[idx].max()), "iters_mean": float(its[idx].mean())}
+    return rep
 
 
 def _gen_worker(args):
@@ -259,6 +361,16 @@ def _cpu_uniform(cfg, per, workers, adj, what):
                       f"{workers} processes, slowest {t:.1f} s"}
 
 
+def _cpu_large(sols0):
+    """The CPU leg of the large workload: the oracle timed on 8 instances (one per process), and the
+    forward error of every path's solution of instance 0 against the oracle's."""
+    from oracle import riccati
+    cpu = _cpu_uniform(4, 1, 8, False, "textbook Riccati route")
+    ref = riccati.solve(synthetic_instance(4, 0))
+    cpu["gpu_vs_oracle_inst0"] = {m: _fwd_err(s_, ref) for m, s_ in sols0.items()}
+    return cpu
+
+
 def _roofline(ms, nbytes, flops, peak_flops_tf):
     """Roofline entry of one launch: HBM-bound if its arithmetic intensity (algorithmic flops per
     algorithmic byte) is below the ridge point of the given matrix-core peak, else compute-bound."""
@@ -285,14 +397,13 @@ def bench_large(args):
     Cholesky and refinement (the reported path), float32 products and plain float64 beside it."""
     import torch
     import paper_2512_09058_amd as L
-    from oracle import riccati
     b, Nn, nx, nu = 64, 1000, 128, 32
     t0 = time.perf_counter()
     data = _gen_uniform(4, b, distinct=args.distinct)
     torch.cuda.synchronize()
     print(f"[bench] generated and uploaded the large workload in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
-    res = {}
+    res, sols0 = {}, {}
     for mode, mi in (("f64", 0), ("mixed_f32", args.max_it), ("mixed_bf16", max(args.max_it, 20))):
         plan = L.Plan(Nn, nx, nu, batch=b, mode=mode)
         plan.set_launch(threads=512)
@@ -319,10 +430,7 @@ def bench_large(args):
         r = {"value": b / ((tf + tsv) * 1e-3), "ms_per_step": tf + tsv, "ms_factor": tf, "ms_solve": tsv,
              "max_rel_res": float(relh.max()), "iters_max": int(its.max().item()),
              "info_ok": bool((info == 0).all().item()), "variant": plan.variant}
-        sol = [L.unpack(plan, n, t, 0) for n, t in (("x", x), ("u", u), ("lam", lam))]
-        ref = riccati.solve(synthetic_instance(4, 0))
-        r["forward_error_inst0"] = float(max(np.abs(a_ - b_).max() for a_, b_ in zip(sol, ref)) /
-                                         max(np.abs(b_).max() for b_ in ref))
+        sols0[mode] = [L.unpack(plan, n, t, 0) for n, t in (("x", x), ("u", u), ("lam", lam))]
         fb = 8 if mode == "f64" else 4
         r["factor_roofline"] = _roofline(tf, algorithmic_bytes_factor(b, Nn, nx, nu, fb), factor_flops(b, Nn, nx, nu),
                                          78.6)
@@ -344,7 +452,7 @@ def bench_large(args):
                         {"bound": "hbm", "kernel": "solve", "achieved": m["solve_GBps_algorithmic"],
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": m["solve_GBps_algorithmic"] / HBM_PEAK_GBS,
                          "traffic": None, "ms_per_launch": m["ms_solve"]}),
-           "cpu_baseline": None if args.no_cpu else _cpu_uniform(4, 1, 8, False, "textbook Riccati route")}
+           "cpu_baseline": None if args.no_cpu else _cpu_large(sols0)}
     print(json.dumps(out))
 
 
@@ -460,7 +568,6 @@ def main():
 
     import synth
     import paper_2512_09058_amd as L
-    from oracle import kkt
 
     if args.workload == "uneven2048":
         return bench_uneven(args)
@@ -483,19 +590,18 @@ def main():
               f"{r['ms_solve']:.3f} ms), max rel_res {r['rel'].max():.2e}, iters max {r['iters'].max()}, "
               f"variant {r['plan'].variant}", file=sys.stderr, flush=True)
 
-    # sampled cross-check with the oracle's own residual routine
-    sample = [0, 1, 777, 2048, 4095]
-    worst = {}
-    for mode, r in res.items():
-        w = 0.0
-        for i in sample:
-            sol = [L.unpack(r["plan"], n, r[n], i) for n in ("x", "u", "lam")]
-            w = max(w, kkt.residual(prob.instance(i), *sol)[1])
-        worst[mode] = w
-
     m, f = res["mixed_f32"], res["f64"]
     ok = all(np.all(r["info"] == 0) and r["rel"].max() <= TOL for r in res.values())
-    cpu = None if args.no_cpu else cpu_baseline(args.cpu_sample)
+    cpu = None
+    if not args.no_cpu:
+        # the CPU leg: the oracle timed on a sample, and its residual routine applied to sampled GPU
+        # solutions of both paths
+        from oracle import kkt
+        cpu = cpu_baseline(args.cpu_sample)
+        cpu["gpu_vs_oracle_sampled"] = {
+            mode: max(kkt.residual(prob.instance(i), *[L.unpack(r["plan"], n, r[n], i) for n in ("x", "u", "lam")])[1]
+                      for i in (0, 1, 777, 2048, 4095))
+            for mode, r in res.items()}
 
     # roofline of the dominant kernel of the reported (mixed) path
     it_mean = float(np.mean(m["iters"]))
@@ -529,9 +635,9 @@ def main():
                    "batch": BATCH, "N": N, "nx": NX, "nu": NU, "tol": TOL, "max_it": args.max_it,
                    "variant": m["plan"].variant},
         "fp64": {"value": BATCH / (f["ms_per_step"] * 1e-3), "ms_per_step": f["ms_per_step"],
-                 "max_rel_res": float(f["rel"].max()), "oracle_rel_res_sampled": worst["f64"], "kernels": f64k},
+                 "max_rel_res": float(f["rel"].max()), "kernels": f64k},
         "mixed": {"max_rel_res": float(m["rel"].max()), "iters_mean": it_mean, "iters_max": int(m["iters"].max()),
-                  "oracle_rel_res_sampled": worst["mixed_f32"], "kernels": mxk},
+                  "kernels": mxk},
         "mixed_over_fp64": f["ms_per_step"] / m["ms_per_step"],
         "equal_residual_ok": bool(ok),
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -158,6 +158,13 @@ int lq_plan_get_launch(const lq_plan* plan, lq_launch* cfg);
 const char* lq_plan_variant(const lq_plan* plan);
 int lq_plan_set_variant(lq_plan* plan, const char* name);
 
+/* Kernel-shape groups of the plan's current variant: a ragged batch on the "tile" variant (no
+ * checkpoints) groups its instances by the kernel shapes sized for them (factor wavefronts,
+ * padded solve sizes), each group one launch per call, heaviest group first, longest instance
+ * first within a group (the per-bucket variants of the uneven-batch scheduling).  Returns the
+ * group count (1: the whole batch in one launch per call), LQ_EINVAL for a NULL plan. */
+int lq_plan_launch_groups(const lq_plan* plan);
+
 /* Factor sweep (backward in time): for k = N-1..0 the stage products and the stage
  * Cholesky, storing L^R_k, L^S_k, L^Q_k in `workspace`; also the backward sweep of the
  * right-hand side (q, r, f) that lq_solve continues.  `info` (device, int32[B]) receives the

@@ -35,6 +35,7 @@ EXPORTS = {
     "lq_plan_offsets": (C.c_int64, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
     "lq_plan_variant": (C.c_char_p, [C.c_void_p]),
     "lq_plan_set_variant": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "lq_plan_launch_groups": (C.c_int, [C.c_void_p]),
     "lq_plan_set_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lq_plan_get_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lq_factor": (C.c_int, [C.c_void_p, C.POINTER(LqData), C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -84,6 +84,11 @@ class Plan:
         check(lib.lq_plan_set_variant(self._h, name.encode()), "lq_plan_set_variant")
         self.variant = lib.lq_plan_variant(self._h).decode()
 
+    @property
+    def launch_groups(self) -> int:
+        """Kernel-shape groups launched per call (see lq_plan_launch_groups)."""
+        return int(_lib.load().lq_plan_launch_groups(self._h))
+
     def set_launch(self, threads: int = 128, persistent: int = 0, blocks_per_cu: int = 0):
         """Launch shape of the general-size kernels (see lq_plan_set_launch)."""
         c = LqLaunch(int(threads), int(persistent), int(blocks_per_cu), 0)

@@ -4,6 +4,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,6 +61,21 @@ hipError_t launch_solve_tckpt(int NXP, int NUP, lq_mode mode, const SolveArgs& a
                               const GenericLaunch& c, hipStream_t st);
 }  // namespace lq
 
+namespace lq {
+// Raise (never lower) a kernel's dynamic-LDS limit: plans of different sizes share the kernels, and
+// a later plan must not lower the limit an earlier one launches with.
+hipError_t raise_lds_limit(const void* kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<const void*, size_t> set;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = set.find(kernel);
+  if (it != set.end() && it->second >= lds) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) set[kernel] = lds;
+  return e;
+}
+}  // namespace lq
+
 using lq::Desc;
 
 static thread_local std::string g_err;
@@ -100,6 +118,16 @@ struct lq_plan {
   int ts_nxp = 0, ts_nup = 0;  // padded sizes of the tile plan's solve kernel (0: generic solve)
   size_t lds_tckpt = 0;        // checkpointed tile plans: LDS of the solve kernel
   int32_t* order_d = nullptr;  // device: instance indices longest first (inside the desc allocation)
+  // Ragged tile plans: instances grouped by kernel shape (factor wavefronts, padded solve sizes),
+  // one launch per group, heaviest group first (empty: one launch for the whole batch).
+  struct Bucket {
+    int waves, nxp, nup;
+    int32_t off, cnt;          // positions [off, off + cnt) of border_d
+    size_t lds_tile;
+    int32_t grid_factor, grid_solve;
+  };
+  std::vector<Bucket> buckets;
+  int32_t* border_d = nullptr;  // device: instance indices grouped by bucket, longest first within
   size_t offCtr = 0;           // workspace: work counters of the persistent kernels
   int cu_count = 0;
   lq_launch launch = {128, 0, 0, 0};
@@ -109,6 +137,16 @@ struct lq_plan {
 // Persistent grid sizes for the plan's launch shape (host queries; done outside the calls so
 // that lq_factor / lq_solve only enqueue kernels and stay capturable in a graph).
 static void update_grids(lq_plan* p) {
+  for (auto& b : p->buckets) {
+    int pf = lq::tile_blocks_per_cu(b.waves, p->mode, b.lds_tile);
+    int ps = lq::tsolve_blocks_per_cu(b.nxp, b.nup, p->mode);
+    if (p->launch.blocks_per_cu > 0) {
+      pf = std::min(pf, (int)p->launch.blocks_per_cu);
+      ps = std::min(ps, (int)p->launch.blocks_per_cu);
+    }
+    b.grid_factor = (int32_t)std::min((int64_t)p->cu_count * pf, (int64_t)b.cnt);
+    b.grid_solve = (int32_t)std::min((int64_t)p->cu_count * ps, (int64_t)b.cnt);
+  }
   for (int f = 0; f < 2; ++f) {
     const size_t lds = f ? p->lds_factor : p->lds_solve;
     int per;
@@ -256,11 +294,12 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   }
   std::stable_sort(order.begin(), order.end(), [&](int32_t a_, int32_t b_) { return cost[a_] > cost[b_]; });
   const size_t descb = align256(sizeof(Desc) * batch);
-  if (hipMalloc((void**)&p->desc_d, descb + sizeof(int32_t) * batch) != hipSuccess) {
+  if (hipMalloc((void**)&p->desc_d, descb + 2 * sizeof(int32_t) * batch) != hipSuccess) {
     delete p;
     return fail(LQ_ENOMEM, "lq_plan_create: descriptor table allocation failed");
   }
   p->order_d = (int32_t*)((char*)p->desc_d + descb);
+  p->border_d = p->order_d + batch;
   if (hipMemcpy(p->desc_d, p->desc_h.data(), sizeof(Desc) * batch, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->order_d, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(p->desc_d);
@@ -292,6 +331,49 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   if (p->can_tile && ckpt_stride > 0 && lq::prepare_tckpt(p->ts_nxp, p->ts_nup, mode, p->lds_tckpt) != hipSuccess) {
     (void)hipGetLastError();
     p->can_tile = false;
+  }
+  // ragged tile plans: one launch per kernel shape (an instance runs with the kernels sized for it,
+  // not for the largest instance of the batch)
+  if (p->can_tile && ckpt_stride == 0 && p->ts_nxp > 0 && !p->uniform) {
+    typedef std::tuple<int, int, int> Key;
+    std::map<Key, std::vector<int32_t>> groups;
+    std::map<Key, double> gcost;
+    for (int32_t i : order) {
+      int nxp = 0, nup = 0;
+      lq::tsolve_sizes(nx[i], nu[i], &nxp, &nup);
+      const Key key(lq::tile_waves((nx[i] + 15) / 16 + (nu[i] + 15) / 16), nxp, nup);
+      groups[key].push_back(i);
+      gcost[key] += cost[i];
+    }
+    if (groups.size() > 1) {
+      std::vector<Key> keys;
+      for (auto& kv : groups) keys.push_back(kv.first);
+      std::stable_sort(keys.begin(), keys.end(), [&](const Key& x_, const Key& y_) { return gcost[x_] > gcost[y_]; });
+      std::vector<int32_t> border;
+      bool ok = true;
+      for (const Key& key : keys) {
+        lq_plan::Bucket b;
+        std::tie(b.waves, b.nxp, b.nup) = key;
+        b.off = (int32_t)border.size();
+        b.cnt = (int32_t)groups[key].size();
+        b.lds_tile = 0;
+        for (int32_t i : groups[key]) {
+          b.lds_tile = std::max(b.lds_tile, lq::tile_lds_bytes(nx[i], nu[i], mode));
+          border.push_back(i);
+        }
+        b.grid_factor = b.grid_solve = b.cnt;
+        if (lq::prepare_tile(b.waves, mode, b.lds_tile) != hipSuccess ||
+            lq::prepare_tsolve(b.nxp, b.nup, mode) != hipSuccess) {
+          (void)hipGetLastError();
+          ok = false;
+        }
+        p->buckets.push_back(b);
+      }
+      if (!ok || hipMemcpy(p->border_d, border.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        p->buckets.clear();
+      }
+    }
   }
   if ((p->variant == VAR_GENERIC && !p->can_generic) || (p->variant == VAR_TILE && !p->can_tile)) {
     hipFree(p->desc_d);
@@ -336,6 +418,19 @@ static lq::GenericLaunch generic_launch(const lq_plan* p, void* ws, bool factor)
     c.counter = (int32_t*)((char*)ws + p->offCtr) + (factor ? 0 : 1);
   }
   return c;
+}
+
+// Launch shape of one bucket's kernels: its slice of the grouped order, its persistent grid.
+static lq::GenericLaunch bucket_launch(const lq_plan* p, void* ws, bool factor, const lq_plan::Bucket& b) {
+  lq::GenericLaunch c = generic_launch(p, ws, factor);
+  c.order = p->border_d + b.off;
+  c.grid = p->launch.persistent ? (factor ? b.grid_factor : b.grid_solve) : b.cnt;
+  return c;
+}
+
+extern "C" int lq_plan_launch_groups(const lq_plan* p) {
+  if (!p) return fail(LQ_EINVAL, "lq_plan_launch_groups: plan is NULL");
+  return p->variant == VAR_TILE && !p->ckpt && !p->buckets.empty() ? (int)p->buckets.size() : 1;
 }
 
 extern "C" void lq_plan_destroy(lq_plan* p) {
@@ -404,7 +499,14 @@ extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* 
   hipError_t e;
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_factor_small(p->mode, p->batch, p->N[0], p->nx[0], p->nu[0], *d, F, V, info, st);
-  else if (p->variant == VAR_TILE)
+  else if (p->variant == VAR_TILE && !p->buckets.empty()) {
+    e = hipSuccess;
+    for (const auto& b : p->buckets) {
+      e = lq::launch_factor_tile(p->mode, b.waves, p->desc_d, b.cnt, *d, F, V, info, b.lds_tile,
+                                 bucket_launch(p, ws, true, b), st);
+      if (e != hipSuccess) break;
+    }
+  } else if (p->variant == VAR_TILE)
     e = lq::launch_factor_tile(p->mode, p->tile_waves, p->desc_d, p->batch, *d, F, V, info, p->lds_tile,
                                generic_launch(p, ws, true), st);
   else
@@ -437,6 +539,15 @@ static hipError_t launch_solve_plan(const lq_plan* p, const lq::SolveArgs& a, vo
   const lq::GenericLaunch c = generic_launch(p, ws, false);
   if (p->variant == VAR_TILE && p->ckpt)
     return lq::launch_solve_tckpt(p->ts_nxp, p->ts_nup, p->mode, a, p->lds_tckpt, c, st);
+  if (p->variant == VAR_TILE && !p->buckets.empty()) {
+    for (const auto& b : p->buckets) {
+      lq::SolveArgs ab = a;
+      ab.batch = b.cnt;
+      const hipError_t e = lq::launch_solve_tsolve(b.nxp, b.nup, p->mode, ab, bucket_launch(p, ws, false, b), st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (p->variant == VAR_TILE && p->ts_nxp) return lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, c, st);
   return lq::launch_solve_generic(p->mode, a, p->lds_solve, c, st);
 }

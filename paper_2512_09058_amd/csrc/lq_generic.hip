@@ -29,6 +29,7 @@
 #include "lq_internal.hpp"
 
 namespace lq {
+hipError_t raise_lds_limit(const void* kernel, size_t lds);  // lq_api.hip
 
 __device__ __forceinline__ double rsqrt_f64(double a) {
   // hardware estimate (~2^-24) and two Newton steps: y <- y (3/2 - a/2 y^2)
@@ -1142,7 +1143,7 @@ hipError_t prepare_generic(bool factor, size_t lds) {
   for (int t : {64, 128, 256, 512})
     for (lq_mode m : {LQ_F64, LQ_MIXED_F32}) {
       hipError_t r =
-          hipFuncSetAttribute(generic_kernel(t, factor, m), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          raise_lds_limit(generic_kernel(t, factor, m), lds);
       if (r != hipSuccess) e = r;
     }
   return e;

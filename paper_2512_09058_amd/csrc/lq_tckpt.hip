@@ -7,6 +7,7 @@
 #include "lq_tsolve.hpp"
 
 namespace lq {
+hipError_t raise_lds_limit(const void* kernel, size_t lds);  // lq_api.hip
 namespace {
 
 // Wavefronts per workgroup for padded sizes NXP, NUP (tile columns NXP/16 + NUP/16).
@@ -63,7 +64,7 @@ size_t tckpt_lds_bytes(int NXP, int NUP, size_t tile_lds) {
 hipError_t prepare_tckpt(int NXP, int NUP, lq_mode mode, size_t lds) {
   const void* k = tc_kernel(NXP, NUP, mode);
   if (!k) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return raise_lds_limit(k, lds);
 }
 
 int tckpt_blocks_per_cu(int NXP, int NUP, lq_mode mode, size_t lds) {

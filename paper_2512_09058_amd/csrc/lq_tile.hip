@@ -2,6 +2,7 @@
 #include "lq_tile_factor.hpp"
 
 namespace lq {
+hipError_t raise_lds_limit(const void* kernel, size_t lds);  // lq_api.hip
 namespace {
 
 // Instances of this workgroup: without a counter the one at position blockIdx.x, with a counter
@@ -98,7 +99,7 @@ size_t tile_lds_bytes(int nx, int nu, lq_mode mode) {
 
 hipError_t prepare_tile(int waves, lq_mode mode, size_t lds) {
   const void* k = waves == 3 ? tile_kernel<3>(mode) : waves == 5 ? tile_kernel<5>(mode) : tile_kernel<10>(mode);
-  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return raise_lds_limit(k, lds);
 }
 
 int tile_blocks_per_cu(int waves, lq_mode mode, size_t lds) {

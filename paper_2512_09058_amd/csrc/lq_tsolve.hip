@@ -2,6 +2,7 @@
 #include "lq_tsolve.hpp"
 
 namespace lq {
+hipError_t raise_lds_limit(const void* kernel, size_t lds);  // lq_api.hip
 namespace {
 
 // Register target: two wavefronts per SIMD (several instances per CU hide each other's latency).
@@ -47,8 +48,7 @@ size_t tsolve_lds_bytes(int NXP, int NUP) {
 }
 
 hipError_t prepare_tsolve(int NXP, int NUP, lq_mode mode) {
-  return hipFuncSetAttribute(ts_kernel(NXP, NUP, mode == LQ_F64), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)tsolve_lds_bytes(NXP, NUP));
+  return raise_lds_limit(ts_kernel(NXP, NUP, mode == LQ_F64), tsolve_lds_bytes(NXP, NUP));
 }
 
 int tsolve_blocks_per_cu(int NXP, int NUP, lq_mode mode) {

@@ -146,3 +146,41 @@ def test_autotuner_records_and_reapplies(tmp_path):
     other = L.Plan(plan.N, plan.nx, plan.nu, mode="f64")
     assert tune.apply_cached(other, path) is not None
     assert other.get_launch() == choice["launch"] and other.variant == choice["variant"]
+
+
+@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 8)])
+def test_ragged_tile_plan_launches_per_kernel_shape(mode, max_it):
+    """A ragged tile plan groups its instances by kernel shape (one launch per group per call): the
+    groups together cover every instance exactly once (each solved, residual certified, oracle
+    checked on a sample), with and without the persistent grid, and agree with the generic
+    variant to rounding.  Uniform and checkpointed plans keep one group."""
+    insts = _ragged_sample(48)
+    shapes = {((p.nx + 15) // 16 + (p.nu + 15) // 16 <= 3, p.nx <= 32, p.nu <= 16) for p in insts}
+    print(f"case: per-shape launches {mode}, {len(shapes)} shape classes", flush=True)
+    data = L.pack(insts)
+    Ns, nxs, nus = [p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts]
+    plan = L.Plan(Ns, nxs, nus, mode=mode)
+    assert plan.variant == "tile" and plan.launch_groups >= 2, plan.launch_groups
+    ref = None
+    for persistent in (1, 0):
+        plan.set_launch(threads=128, persistent=persistent, blocks_per_cu=0)
+        x, u, lam, rel, info, its = _solve(plan, data, max_it)
+        assert np.all(info == 0) and rel.max() <= 1e-10, (info, rel.max())
+        sols = [(L.unpack(plan, "x", x, i), L.unpack(plan, "u", u, i), L.unpack(plan, "lam", lam, i))
+                for i in range(len(insts))]
+        if ref is None:
+            ref = sols
+        else:
+            for a_, b_ in zip(sols, ref):
+                assert all(np.array_equal(p_, q_) for p_, q_ in zip(a_, b_))
+    for i in (0, 7, 23, 47):
+        assert kkt.residual(insts[i], *ref[i])[1] <= 1e-10, i
+    gplan = L.Plan(Ns, nxs, nus, mode=mode)
+    gplan.set_variant("generic")
+    assert gplan.launch_groups == 1
+    gx, gu, glam, grel, ginfo, _ = _solve(gplan, data, max_it)
+    for i in range(len(insts)):
+        g = (L.unpack(gplan, "x", gx, i), L.unpack(gplan, "u", gu, i), L.unpack(gplan, "lam", glam, i))
+        assert forward_error(ref[i], g) <= 1e-8, i
+    assert L.Plan(20, 30, 8, batch=5, mode=mode).launch_groups == 1
+    assert L.Plan(Ns, nxs, nus, mode=mode, ckpt_stride=5).launch_groups == 1

@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
 
   for (int k = N - 1; k >= 0; --k) {
     sd.store(sC, sH, sRQ, sFv, L, true);
-    if (k > 0) sd.load(d, N, L, batch, k - 1, true);
+    sd.load(d, N, L, batch, k > 0 ? k - 1 : 0, true);
     // operands of stage k from LDS
     constexpr int RSP = SH::RSP;
     const double* pc = sC + g * LC + ia;          // column ia of C: pc[m * RSP]
@@ -370,7 +370,9 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
 #pragma unroll
     for (int j = 0; j < NUX; ++j) {
       const double col = pk[j * RSP];
-      const double v = (!isu && j < NU) ? col : 0.5 * (pr[j] + col);
+      const double rj = pr[j];  // read on every lane: a read under a condition waits at once
+      const double sym = 0.5 * (rj + col);
+      const double v = (!isu && j < NU) ? col : sym;
       h[j] = j <= i ? v : 0.0;
     }
     const double rqv = sRQ[g * NUX + ia];
@@ -479,10 +481,13 @@ struct SolveCtx {
   double *sC, *sH, *sRQ, *sFv;
 };
 
-// Per-lane operands of forward stage k (contiguous per instance), loaded a stage ahead.
+// Per-lane operands of forward stage k (contiguous per instance), loaded a stage ahead.  The
+// loads are plain (no arithmetic or selection on the loaded values here): an operation on a
+// loaded value placed next to its load makes the wavefront wait for that load at once.
 struct FwdVec {
-  double s0;          // input lanes: rbar_k[ic];  state lanes: f_k[mi] (mode 0) or flam_k[mi]
-  double s1;          // state lanes: p_{k+1}[mi]
+  double rv;          // rbar_k[ic] (used on input lanes)
+  double fv;          // f_k[mi] (mode 0) or flam_k[mi] (used on state lanes)
+  double s1;          // p_{k+1}[mi]
   double zu, zx, zl;  // old iterate (correction passes): u_k[ic], x_{k+1}[mi], lam_k[mi]
 };
 
@@ -491,11 +496,9 @@ __device__ __forceinline__ void load_fwdvec(FwdVec& v, const SolveCtx<NX, NU, TF
   const Lane& L = s.L;
   const double* rbv = mode == 0 ? s.rb0 : s.rb2;
   const double* pvv = mode == 0 ? s.p0 : s.p2;
-  double fv;
-  if (mode == 0) fv = HF ? s.d.f[(L.bb * s.N + k) * NX + L.mi] : 0.0;
-  else fv = s.flam[(int64_t)k * NX + L.mi];
-  const double rv = rbv[(int64_t)k * NU + L.ic];
-  v.s0 = L.isu ? rv : fv;
+  if (mode == 0) v.fv = HF ? s.d.f[(L.bb * s.N + k) * NX + L.mi] : 0.0;
+  else v.fv = s.flam[(int64_t)k * NX + L.mi];
+  v.rv = rbv[(int64_t)k * NU + L.ic];
   v.s1 = pvv[(int64_t)(k + 1) * NX + L.mi];
   if (mode == 1) {
     v.zu = s.u[(int64_t)k * NU + L.ic];
@@ -529,37 +532,31 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
   double lkm = 0.0;                              // updated lam_{k-1}
   double mr = 0.0, mb = 0.0;
 
-  // prologue: factor slots 0, 1 and stage-0 data in LDS; stage-1 data and F_2 in flight
+  // prologue: F_0 in LDS slot 0; stage-0 data and F_1 in flight.  Every stage then runs the same
+  // code: no load of the loop sits under a condition (the prefetch index is clamped instead, so
+  // the last stage fetches a block again), since a conditional load makes the wavefront wait for
+  // every load in flight where the paths join.
   {
-    FSeg<NX, NU, TF> f0, f1;
+    FSeg<NX, NU, TF> f0;
     f0.load(s.F, fistr, L, batch, 0);
-    f1.load(s.F, fistr, L, batch, 1);
-    StageData<NX, NU, HS, HF> d0;
-    d0.load(s.d, N, L, batch, 0, res);
     f0.store(s.sF, L);
-    f1.store(s.sF + 4 * FS, L);
-    d0.store(s.sC, s.sH, s.sRQ, s.sFv, L, res);
   }
   FSeg<NX, NU, TF> fn;
   StageData<NX, NU, HS, HF> dn;
-  if (N > 1) {
-    dn.load(s.d, N, L, batch, 1, res);
-    fn.load(s.F, fistr, L, batch, 2);
-  }
+  dn.load(s.d, N, L, batch, 0, true);
+  fn.load(s.F, fistr, L, batch, 1);
   FwdVec cur, nxt;
   load_fwdvec<NX, NU, TF, HS, HF>(cur, s, 0, mode);
 
   for (int k = 0; k < N; ++k) {
-    if (k > 0) {
-      // stage k data and F_{k+1} into LDS (slot (k+1) & 1 held F_{k-1}, no longer needed)
-      dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, res);
-      fn.store(s.sF + ((k + 1) & 1) * 4 * FS, L);
-      if (k + 1 < N) {
-        dn.load(s.d, N, L, batch, k + 1, res);
-        fn.load(s.F, fistr, L, batch, k + 2);
-      }
-    }
-    if (k + 1 < N) load_fwdvec<NX, NU, TF, HS, HF>(nxt, s, k + 1, mode);
+    // stage k data and F_{k+1} into LDS (slot (k+1) & 1 held F_{k-1}, no longer needed), then
+    // stage k + 1 in flight
+    dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, true);
+    fn.store(s.sF + ((k + 1) & 1) * 4 * FS, L);
+    const int kn = k + 1 < N ? k + 1 : N - 1;
+    dn.load(s.d, N, L, batch, kn, true);
+    fn.load(s.F, fistr, L, batch, k + 2 <= N ? k + 2 : N);
+    load_fwdvec<NX, NU, TF, HS, HF>(nxt, s, kn, mode);
     constexpr int RSP = SH::RSP;
     const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;          // F_k of this instance
     const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;   // F_{k+1}
@@ -567,7 +564,7 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     const double* prA = s.sC + g * LC + mi * RSP;              // row mi of C = [B row, A row]
 
     // t = rbar + L^S^T x on input lanes
-    double ta[3] = {cur.s0, 0.0, 0.0};
+    double ta[3] = {cur.rv, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       const double xb = bc(xc, NU + m);
@@ -586,7 +583,7 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     }
     const double du = -uu;
     // x_{k+1} = A x + B u + f on state lanes
-    double xa[3] = {cur.s0, 0.0, 0.0};
+    double xa[3] = {cur.fv, 0.0, 0.0};
 #pragma unroll
     for (int n = 0; n < NX; ++n) {
       const double xb = bc(xc, NU + n);
@@ -595,20 +592,24 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
 #pragma unroll
     for (int j = 0; j < NU; ++j) xa[(NX + j) % 3] = fma(prA[j], bc(du, j), xa[(NX + j) % 3]);
     const double xn = xa[0] + (xa[1] + xa[2]);
-    // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}; coefficients masked to the triangle
+    // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}; coefficients masked to the triangle (the
+    // reads outside it stay inside the stage's L^Q block and are zeroed by a select, so that no
+    // read sits under a condition)
     const TF* lqc = Fk1 + SH::OLQ + mi;                    // column mi: + m(m+1)/2
     const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;     // row mi: + j
     double t2a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double cm = (m >= mi) ? (double)lqc[m * (m + 1) / 2] : 0.0;
+      const double lv = (double)lqc[m * (m + 1) / 2];
+      const double cm = (m >= mi) ? lv : 0.0;
       t2a[m % 3] = fma(cm, bc(xn, NU + m), t2a[m % 3]);
     }
     const double t2 = t2a[0] + (t2a[1] + t2a[2]);
     double lma[3] = {cur.s1, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      const double cj = (j <= mi) ? (double)lqr[j] : 0.0;
+      const double lv = (double)lqr[j];
+      const double cj = (j <= mi) ? lv : 0.0;
       lma[j % 3] = fma(cj, bc(t2, NU + j), lma[j % 3]);
     }
     const double lm = lma[0] + (lma[1] + lma[2]);
@@ -678,7 +679,7 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     xc = xn;
     xk = xnew;
     lkm = lnew;
-    if (k + 1 < N) cur = nxt;
+    cur = nxt;
   }
   if (res) {
     // stage N: Q_N x_N - lam_{N-1} = -q_N
@@ -723,41 +724,31 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
   const int64_t fistr = (int64_t)(N + 1) * FS;
   double p2n = -s.rhox[(int64_t)N * NX + mi];
   if (xl) s.p2[(int64_t)N * NX + mi] = p2n;
+  // prologue: F_N in LDS; F_{N-1} and stage N-1 in flight; then the same code every stage, with
+  // clamped, unconditional prefetches (see fwd_res)
   {
-    FSeg<NX, NU, TF> fa, fb;
+    FSeg<NX, NU, TF> fa;
     fa.load(s.F, fistr, L, batch, N);
-    fb.load(s.F, fistr, L, batch, N - 1);
-    StageData<NX, NU, HS, HF> d0;
-    d0.load(s.d, N, L, batch, N - 1, false);
     fa.store(s.sF + (N & 1) * 4 * FS, L);
-    fb.store(s.sF + ((N - 1) & 1) * 4 * FS, L);
-    d0.store(s.sC, s.sH, s.sRQ, s.sFv, L, false);
   }
   FSeg<NX, NU, TF> fn;
   StageData<NX, NU, HS, HF> dn;
-  if (N > 1) {
-    fn.load(s.F, fistr, L, batch, N - 2);
-    dn.load(s.d, N, L, batch, N - 2, false);
-  }
+  fn.load(s.F, fistr, L, batch, N - 1);
+  dn.load(s.d, N, L, batch, N - 1, false);
   // (the lane's residual entry is read through a selected address: selecting between two loaded
   // values would wait for both right after they are issued)
   double rho = *(isu ? s.rhou + (int64_t)(N - 1) * NU + ic : s.rhox + (int64_t)(N - 1) * NX + mi);
   double fl = s.flam[(int64_t)(N - 1) * NX + mi];
   for (int k = N - 1; k >= 0; --k) {
-    if (k < N - 1) {
-      // F_k into slot k & 1 (held F_{k+2}, no longer needed), stage-k data into LDS
-      fn.store(s.sF + (k & 1) * 4 * FS, L);
-      dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, false);
-      if (k > 0) {
-        fn.load(s.F, fistr, L, batch, k - 1);
-        dn.load(s.d, N, L, batch, k - 1, false);
-      }
-    }
-    double rho_n = 0.0, fl_n = 0.0;
-    if (k > 0) {
-      rho_n = *(isu ? s.rhou + (int64_t)(k - 1) * NU + ic : s.rhox + (int64_t)(k - 1) * NX + mi);
-      fl_n = s.flam[(int64_t)(k - 1) * NX + mi];
-    }
+    // F_k into slot k & 1 (held F_{k+2}, no longer needed), stage-k data into LDS, then stage
+    // k - 1 in flight
+    fn.store(s.sF + (k & 1) * 4 * FS, L);
+    dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, false);
+    const int kp = k > 0 ? k - 1 : 0;
+    fn.load(s.F, fistr, L, batch, kp);
+    dn.load(s.d, N, L, batch, kp, false);
+    const double rho_n = *(isu ? s.rhou + (int64_t)kp * NU + ic : s.rhox + (int64_t)kp * NX + mi);
+    const double fl_n = s.flam[(int64_t)kp * NX + mi];
     constexpr int RSP = SH::RSP;
     const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;
     const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;
@@ -767,14 +758,16 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
     double t1a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double cm = (m >= mi) ? (double)lqc[m * (m + 1) / 2] : 0.0;
+      const double lv = (double)lqc[m * (m + 1) / 2];
+      const double cm = (m >= mi) ? lv : 0.0;
       t1a[m % 3] = fma(cm, bc(fl, NU + m), t1a[m % 3]);
     }
     const double t1 = t1a[0] + (t1a[1] + t1a[2]);
     double wa[3] = {p2n, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      const double cj = (j <= mi) ? (double)lqr[j] : 0.0;
+      const double lv = (double)lqr[j];
+      const double cj = (j <= mi) ? lv : 0.0;
       wa[j % 3] = fma(cj, bc(t1, NU + j), wa[j % 3]);
     }
     const double w = wa[0] + (wa[1] + wa[2]);

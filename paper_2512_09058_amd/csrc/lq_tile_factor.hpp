@@ -301,7 +301,9 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
     // Symmetric part of [[R,S],[S^T,Q]] (padded) in the float64 fragment layout, tile (bb, aa):
     // at stage N only the state block (Q_N), at stage 0 only the input rows.
     auto load_h = [&](int bb, int aa) -> d4 {
-      // branch-free within the wavefront: clamped addresses, out-of-range entries selected away
+      // branch-free within the wavefront: clamped addresses, out-of-range entries zeroed through
+      // an opaque mask (a select on a loaded value compiles to a branch around the load, which
+      // waits for it at once), the identity of the padding added
       d4 h = d4{0, 0, 0, 0};
       const bool bu = bb < TU, au = aa < TU;
       const int ib = (bu ? 16 * bb : 16 * (bb - TU)) + g, jb = (au ? 16 * aa : 16 * (aa - TU)) + c;
@@ -311,8 +313,8 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int ii = ib + 4 * t, ic = min(ii, nu - 1);
-            const double v = 0.5 * (Rk[ic * nu + jc] + Rk[jc * nu + ic]);
-            h[t] = (ii < nu && jb < nu) ? v : (ii == jb ? 1.0 : 0.0);
+            const bool in = ii < nu && jb < nu;
+            h[t] = keep_if(in, 0.5 * (Rk[ic * nu + jc] + Rk[jc * nu + ic])) + (!in && ii == jb ? 1.0 : 0.0);
           }
         }
       } else if (bu) {
@@ -321,8 +323,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int ii = ib + 4 * t, ic = min(ii, nu - 1);
-            const double v = Sk[ic * nx + jc];
-            h[t] = (ii < nu && jb < nx) ? v : 0.0;
+            h[t] = keep_if(ii < nu && jb < nx, Sk[ic * nx + jc]);
           }
         }
       } else if (k > 0) {
@@ -330,8 +331,8 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int ii = ib + 4 * t, ic = min(ii, nx - 1);
-          const double v = 0.5 * (Qk[ic * nx + jc] + Qk[jc * nx + ic]);
-          h[t] = (ii < nx && jb < nx) ? v : (ii == jb ? 1.0 : 0.0);
+          const bool in = ii < nx && jb < nx;
+          h[t] = keep_if(in, 0.5 * (Qk[ic * nx + jc] + Qk[jc * nx + ic])) + (!in && ii == jb ? 1.0 : 0.0);
         }
       }
       return h;
@@ -347,6 +348,16 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           if (bb <= a) G[bb] = load_h(bb, a);
       }
     } else {
+      // Up to five tile columns the H tiles are fetched here, so that their reads overlap the
+      // trmm below (for more columns the registers they would hold across it are not free).
+      constexpr bool EARLY_H = TMAX <= 5;
+      if constexpr (EARLY_H) {
+        if (own) {
+#pragma unroll
+          for (int bb = 0; bb < TMAX; ++bb)
+            if (bb <= a) G[bb] = load_h(bb, a);
+        }
+      }
       // ---- w = L^Q_{k+1} (L^Q_{k+1})^T f_k + p_{k+1}
       if (!rhs) {
       } else if (fg) {
@@ -378,13 +389,19 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
       const bool colok = col < ncol;
       const int r0 = MM<TP>::row(0, g);  // row(t, g) = r0 + row(t, 0)
       const double* cb = (ucol ? Bk : Ak) + min(col, ncol - 1);
+      // right-hand-side entry of this lane's column (r_k or q_k), read now and used after the
+      // trmm; the address is selected, not the value
+      const double base_raw = rhs ? *(ucol ? rg + (int64_t)k * nu + min(col, nu - 1)
+                                           : qg + (int64_t)k * nx + min(col, nx - 1))
+                                  : 0.0;
+      // (always issued, with a clamped slab index where the slab lies past the last one: a load
+      // under a condition, or a select on its value, makes the wavefront wait for it at once)
       auto load_c = [&](int mp) -> d4 {
         d4 v;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int row = r0 + 16 * mp + MM<TP>::row(t, 0);
-          const double e = cb[min(row, nx - 1) * ldc];
-          v[t] = (colok && row < nx) ? e : 0.0;
+          v[t] = keep_if(colok && row < nx, cb[min(row, nx - 1) * ldc]);
         }
         return v;
       };
@@ -395,10 +412,15 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
       for (int m = 0; m < TX; ++m) {
         PV Wf = PV{0, 0, 0, 0};
         if (own) {
+          // unrolled, with an exit instead of a guarded body, so that the fragments in flight
+          // rotate by renaming: a register copy of a fragment would wait for its load
           d4 cur = load_c(m);
-          d4 nxt = m + 1 < TX ? load_c(m + 1) : d4{0, 0, 0, 0};
-          for (int mp = m; mp < TX; ++mp) {
-            const d4 nn = mp + 2 < TX ? load_c(mp + 2) : d4{0, 0, 0, 0};
+          d4 nxt = load_c(min(m + 1, TX - 1));
+#pragma unroll
+          for (int q = 0; q < TMAX - 1; ++q) {
+            const int mp = m + q;
+            if (mp >= TX) break;
+            const d4 nn = load_c(min(mp + 2, TX - 1));
             if (rhs && m == 0) {
 #pragma unroll
               for (int t = 0; t < 4; ++t) part = fma(cur[t], wv[16 * mp + r0 + MM<TP>::row(t, 0)], part);
@@ -425,22 +447,14 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
       if (rhs && own) {
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
-        if (g == 0) {
-          double base = 0.0;
-          if (ucol) {
-            if (col < nu) base = rg[(int64_t)k * nu + col];
-          } else if (k > 0 && col < nx) {
-            base = qg[(int64_t)k * nx + col];
-          }
-          rq[16 * a + c] = base + part;
-        }
+        if (g == 0) rq[16 * a + c] = keep_if(ucol ? col < nu : (k > 0 && col < nx), base_raw) + part;
       }
       // ---- G = [[R,S],[S^T,Q]] + W^T W in float64 (mixed: float32 layout -> float64 layout)
       if (own) {
 #pragma unroll
         for (int bb = 0; bb < TMAX; ++bb) {
           if (bb <= a) {
-            const d4 h = load_h(bb, a);
+            const d4 h = EARLY_H ? G[bb] : load_h(bb, a);
             if constexpr (F64) {
               G[bb] = h + Gs[bb];
             } else {

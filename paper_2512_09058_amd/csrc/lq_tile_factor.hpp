@@ -180,22 +180,20 @@ __device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c) {
   return ok ? 0 : (fin ? 1 : 2);
 }
 
-// Row c of X = L^{-1} in lane c of each 16-lane row, from L held one row per lane (h[k] = L[c][k]
-// for k <= c, as chol16 leaves it) and dinv = 1 / L[c][c]:
-//   X[c] = dinv e_c - sum_{k<c} (dinv L[c][k]) X[k],
+// Columns 4g .. 4g+3 of row c of X = L^{-1} in lane c of 16-lane row g, from L held one row per
+// lane (h[k] = L[c][k] for k <= c, as chol16 leaves it) and dinv = 1 / L[c][c]:
+//   X[c][q] = dinv delta_cq - sum_{k<c} (dinv L[c][k]) X[k][q],
 // with the rows X[k] taken in order k = 0, 1, ... by row broadcasts (row k is final once the steps
-// before it are done).  Registers and DPP only.
-__device__ __forceinline__ void inv16_rows(double (&x)[16], const double (&h)[16], double dinv, int c) {
-  double m[16];
+// before it are done).  Each lane group forms its own four columns; entries above the diagonal
+// are zero and stay zero, so all columns run the same steps.  Registers and DPP only.
+__device__ __forceinline__ void inv16_cols4(double (&x)[4], const double (&h)[16], double dinv, int c, int g) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    m[k] = k < c ? dinv * h[k] : 0.0;
-    x[k] = k == c ? dinv : 0.0;
-  }
+  for (int qq = 0; qq < 4; ++qq) x[qq] = 4 * g + qq == c ? dinv : 0.0;
 #pragma unroll
   for (int k = 0; k < 15; ++k) {
+    const double mk = k < c ? dinv * h[k] : 0.0;
 #pragma unroll
-    for (int q = 0; q <= k; ++q) x[q] = fma(-m[k], bc(x[q], k), x[q]);
+    for (int qq = 0; qq < 4; ++qq) x[qq] = fma(-mk, bc(x[qq], k), x[qq]);
   }
 }
 
@@ -503,10 +501,10 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           }
           if (g == 0) dv[16 * j + c] = dinv;
           // X = L_jj^{-1}; DI holds X^T row-major (row q = column q of X: DI[q][c] = X[c][q])
-          double x[16];
-          inv16_rows(x, h, dinv, c);
+          double x[4];
+          inv16_cols4(x, h, dinv, c, g);
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq) DI[(4 * g + qq) * LD + c] = pick4(x, g, qq);
+          for (int qq = 0; qq < 4; ++qq) DI[(4 * g + qq) * LD + c] = x[qq];
         }
         // column j is complete: none of its tiles is read again, and redefining them here lets
         // the diagonal step reuse their registers
@@ -550,9 +548,13 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           // contributions of the rows of earlier passes
           for (int jj = 0; jj < i0; ++jj)
             if (i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * rb[jj];
+          // (the coefficient is read on every lane, at a clamped row, and applied through a select:
+          // a read under a condition waits for itself at once)
+          const int ic = min(i, nu - 1);
           for (int jj = i0; jj < nu && jj < i0 + 64; ++jj) {
             const double y = lane_bcast(acc * di, jj - i0);
-            if (i > jj && i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * y;
+            const double lv = (double)(TF)upan(jj >> 4, ic >> 4)[(jj & 15) * LD + (ic & 15)];
+            acc = (i > jj && i < nu) ? acc - lv * y : acc;
           }
           if (i < nu) {
             const double v = acc * di;

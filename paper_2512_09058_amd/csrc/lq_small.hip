@@ -549,6 +549,17 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
   load_fwdvec<NX, NU, TF, HS, HF>(cur, s, 0, mode);
 
   for (int k = 0; k < N; ++k) {
+    // The lane's entries of F_k that start the recursion (in LDS since the previous stage) are
+    // read first, in one batch: the empty asm with a memory clobber keeps the compiler from
+    // sinking each read to its use, where every read would wait for itself.
+    const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;  // F_k of this instance
+    TF fls[NX], flr[NU];
+#pragma unroll
+    for (int m = 0; m < NX; ++m) fls[m] = Fk[SH::OLS + m * NU + ic];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) flr[j] = Fk[j * (j + 1) / 2 + ic];  // L^R[j][ic] for ic < j
+    const TF fdr = Fk[SH::ODR + ic];
+    asm volatile("" ::: "memory");
     // stage k data and F_{k+1} into LDS (slot (k+1) & 1 held F_{k-1}, no longer needed), then
     // stage k + 1 in flight
     dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, true);
@@ -558,7 +569,6 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
     fn.load(s.F, fistr, L, batch, k + 2 <= N ? k + 2 : N);
     load_fwdvec<NX, NU, TF, HS, HF>(nxt, s, kn, mode);
     constexpr int RSP = SH::RSP;
-    const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;          // F_k of this instance
     const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;   // F_{k+1}
     const double* prC = s.sC + g * LC + ia;                    // column ia of C (stride RSP)
     const double* prA = s.sC + g * LC + mi * RSP;              // row mi of C = [B row, A row]
@@ -568,17 +578,17 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       const double xb = bc(xc, NU + m);
-      ta[m % 3] = fma((double)Fk[SH::OLS + m * NU + ic], xb, ta[m % 3]);
+      ta[m % 3] = fma((double)fls[m], xb, ta[m % 3]);
     }
     double t = ta[0] + (ta[1] + ta[2]);
     // u' = L^R^{-T} t, u = -u'
-    const double dRi = (double)Fk[SH::ODR + ic];
+    const double dRi = (double)fdr;
     double uu = 0.0;
 #pragma unroll
     for (int j = NU - 1; j >= 0; --j) {
       const double uj = bc(t * dRi, j);
       uu = (i == j) ? uj : uu;
-      const double e = (double)Fk[j * (j + 1) / 2 + ic];  // L^R[j][ic] for ic < j (in-block otherwise)
+      const double e = (double)flr[j];  // L^R[j][ic] for ic < j (in-block otherwise)
       t = fma((i < j) ? -e : 0.0, uj, t);
     }
     const double du = -uu;
@@ -740,6 +750,16 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
   double rho = *(isu ? s.rhou + (int64_t)(N - 1) * NU + ic : s.rhox + (int64_t)(N - 1) * NX + mi);
   double fl = s.flam[(int64_t)(N - 1) * NX + mi];
   for (int k = N - 1; k >= 0; --k) {
+    // the lane's L^Q_{k+1} coefficients (in LDS since the previous stage) read first, in one batch
+    // (see fwd_res); the ones outside the triangle stay inside the block and are masked below
+    const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;
+    TF lqc[NX], lqr[NX];
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+      lqc[m] = Fk1[SH::OLQ + mi + m * (m + 1) / 2];  // column mi
+      lqr[m] = Fk1[SH::OLQ + mi * (mi + 1) / 2 + m];  // row mi
+    }
+    asm volatile("" ::: "memory");
     // F_k into slot k & 1 (held F_{k+2}, no longer needed), stage-k data into LDS, then stage
     // k - 1 in flight
     fn.store(s.sF + (k & 1) * 4 * FS, L);
@@ -751,14 +771,18 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
     const double fl_n = s.flam[(int64_t)kp * NX + mi];
     constexpr int RSP = SH::RSP;
     const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;
-    const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;
+    // input lanes: row ic of L^R (packed); state lanes: row mi of L^S (read in one batch)
+    const TF* hp = isu ? Fk + ic * (ic + 1) / 2 : Fk + SH::OLS + mi * NU;
+    TF hrow[NU];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) hrow[j] = hp[j];
+    const TF fdr = Fk[SH::ODR + ic];
+    asm volatile("" ::: "memory");
     // t1 = L^Q_{k+1}^T f', w = L^Q_{k+1} t1 + p2_{k+1} (coefficients masked to the triangle)
-    const TF* lqc = Fk1 + SH::OLQ + mi;
-    const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;
     double t1a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double lv = (double)lqc[m * (m + 1) / 2];
+      const double lv = (double)lqc[m];
       const double cm = (m >= mi) ? lv : 0.0;
       t1a[m % 3] = fma(cm, bc(fl, NU + m), t1a[m % 3]);
     }
@@ -776,13 +800,11 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
 #pragma unroll
     for (int m = 0; m < NX; ++m) tqa[m % 3] = fma(prC[m * RSP], bc(w, NU + m), tqa[m % 3]);
     double tq = tqa[0] + (tqa[1] + tqa[2]);
-    // input lanes: row ic of L^R (packed); state lanes: row mi of L^S
-    const TF* hp = isu ? Fk + ic * (ic + 1) / 2 : Fk + SH::OLS + mi * NU;
-    const double dr = (double)Fk[SH::ODR + ic];
+    const double dr = (double)fdr;
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
       const double rb = bc(tq * dr, j);
-      const double hv = (double)hp[j];
+      const double hv = (double)hrow[j];
       tq = (i > j) ? fma(-hv, rb, tq) : tq;
     }
     if (ul) s.rb2[(int64_t)k * NU + ic] = tq * dr;

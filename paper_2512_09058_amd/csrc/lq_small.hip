@@ -592,25 +592,33 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       t = fma((i < j) ? -e : 0.0, uj, t);
     }
     const double du = -uu;
+    // The lane's row of C_k = [B_k A_k] and its L^Q_{k+1} coefficients (column and row mi; the
+    // ones outside the triangle stay inside the block and are masked below), read in one batch.
+    double pa[NUX];
+    TF lqc[NX], lqr[NX];
+#pragma unroll
+    for (int j = 0; j < NUX; ++j) pa[j] = prA[j];
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+      lqc[m] = Fk1[SH::OLQ + mi + m * (m + 1) / 2];
+      lqr[m] = Fk1[SH::OLQ + mi * (mi + 1) / 2 + m];
+    }
+    asm volatile("" ::: "memory");
     // x_{k+1} = A x + B u + f on state lanes
     double xa[3] = {cur.fv, 0.0, 0.0};
 #pragma unroll
     for (int n = 0; n < NX; ++n) {
       const double xb = bc(xc, NU + n);
-      xa[n % 3] = fma(prA[NU + n], xb, xa[n % 3]);
+      xa[n % 3] = fma(pa[NU + n], xb, xa[n % 3]);
     }
 #pragma unroll
-    for (int j = 0; j < NU; ++j) xa[(NX + j) % 3] = fma(prA[j], bc(du, j), xa[(NX + j) % 3]);
+    for (int j = 0; j < NU; ++j) xa[(NX + j) % 3] = fma(pa[j], bc(du, j), xa[(NX + j) % 3]);
     const double xn = xa[0] + (xa[1] + xa[2]);
-    // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}; coefficients masked to the triangle (the
-    // reads outside it stay inside the stage's L^Q block and are zeroed by a select, so that no
-    // read sits under a condition)
-    const TF* lqc = Fk1 + SH::OLQ + mi;                    // column mi: + m(m+1)/2
-    const TF* lqr = Fk1 + SH::OLQ + mi * (mi + 1) / 2;     // row mi: + j
+    // lam = L^Q_{k+1} (L^Q_{k+1}^T x_{k+1}) + p_{k+1}; coefficients masked to the triangle
     double t2a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double lv = (double)lqc[m * (m + 1) / 2];
+      const double lv = (double)lqc[m];
       const double cm = (m >= mi) ? lv : 0.0;
       t2a[m % 3] = fma(cm, bc(xn, NU + m), t2a[m % 3]);
     }
@@ -633,8 +641,18 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       s.lam[(int64_t)k * NX + mi] = lnew;
     }
     if (res) {
-      const double* hr = s.sH + g * LH + ia * RSP;   // row ia of H
-      const double* hc = s.sH + g * LH + ia;         // column ia of H (stride RSP)
+      // row and column ia of H and column ia of C, read in one batch
+      const double* hrp = s.sH + g * LH + ia * RSP;
+      const double* hcp = s.sH + g * LH + ia;
+      double hr[NUX], hcs[NUX], pcv[NX];
+#pragma unroll
+      for (int j = 0; j < NUX; ++j) {
+        hr[j] = hrp[j];
+        hcs[j] = hcp[j * RSP];
+      }
+#pragma unroll
+      for (int n = 0; n < NX; ++n) pcv[n] = prC[n * RSP];
+      asm volatile("" ::: "memory");
       // residual rows of stage k at the updated iterate (x_k = xk, u_k, lam_k, x_{k+1}, lam_{k-1})
       double au[2] = {0.0, 0.0};   // input lanes: S x_k ; R u
       double ab[2] = {0.0, 0.0};   // column ia of C times lam: B^T lam (input) / A^T lam (state)
@@ -644,10 +662,10 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
       for (int n = 0; n < NX; ++n) {
         const double xb = bc(xk, NU + n);
         const double lb = bc(lnew, NU + n);
-        const double hrow = hr[NU + n], hcol = hc[(NU + n) * RSP];
+        const double hrow = hr[NU + n], hcol = hcs[NU + n];
         if (HS) au[0] = fma(hrow, xb, au[0]);
-        ab[n & 1] = fma(prC[n * RSP], lb, ab[n & 1]);
-        al[0] = fma(prA[NU + n], xb, al[0]);
+        ab[n & 1] = fma(pcv[n], lb, ab[n & 1]);
+        al[0] = fma(pa[NU + n], xb, al[0]);
         ax[0] = fma(0.5 * (hrow + hcol), xb, ax[0]);
       }
       const double bu = (k == 0 && HS) ? au[0] : 0.0;   // S_0 x_init
@@ -655,9 +673,9 @@ __device__ double fwd_res(const SolveCtx<NX, NU, TF, HS, HF>& s, int mode, bool 
 #pragma unroll
       for (int j = 0; j < NU; ++j) {
         const double ub = bc(unew, j);
-        const double hrow = hr[j], hcol = hc[j * RSP];
+        const double hrow = hr[j], hcol = hcs[j];
         au[1] = fma(0.5 * (hrow + hcol), ub, au[1]);
-        al[1] = fma(prA[j], ub, al[1]);
+        al[1] = fma(pa[j], ub, al[1]);
         if (HS) ax[1] = fma(hcol, ub, ax[1]);
       }
       const double abt = ab[0] + ab[1];

@@ -220,9 +220,14 @@ def bench_uneven(args):
         out["mixed_f32"]["buckets"][f"nx {lo}-{hi}"]["max_fwd_err_vs_f64_gpu"] = dev
         print(f"[bench] uneven bucket nx {lo}-{hi}: {len(idx)} instances, mixed vs f64 {dev:.1e}",
               file=sys.stderr, flush=True)
-    out["value"] = out["mixed_f32"]["value"]
-    out["roofline"] = out["mixed_f32"]["roofline"]
-    out["cpu_baseline"] = None if args.no_cpu else _cpu_uneven(insts, sols)
+    m = out["mixed_f32"]
+    out.update({"value": m["value"], "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32 stage products + f64 Cholesky/residual/refinement",
+                "config": {"workload": "uneven batch of 2048 LQ problems, nx 6..64, nu 2..16, N 10..200, "
+                                       "hipGraph replay", "batch": 2048, "tol": TOL, "max_it": args.max_it},
+                "roofline": m["roofline"],
+                "cpu_baseline": None if args.no_cpu else _cpu_uneven(insts, sols)})
     print(json.dumps(out))
 
 

@@ -424,8 +424,12 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
     }
     // potrf (float64); at k = 0 only the nu input columns
     int bad;
-    if (k > 0) bad = potrf_rows<NUX, NUX>(h, mydinv, i);
-    else bad = potrf_rows<NUX, NU>(h, mydinv, i);
+    // (the row index through an opaque copy: otherwise the compiler keeps the sixteen lane masks
+    // of the unrolled Cholesky live across the stage loop and spills them)
+    int io = i;
+    asm volatile("" : "+v"(io));
+    if (k > 0) bad = potrf_rows<NUX, NUX>(h, mydinv, io);
+    else bad = potrf_rows<NUX, NU>(h, mydinv, io);
     if (bad && code == 0) code = bad == 2 ? LQ_INFO_NONFINITE : k + 1;
 #pragma unroll
     for (int j = 0; j < NUX; ++j) h[j] = rnd<TF>(h[j]);

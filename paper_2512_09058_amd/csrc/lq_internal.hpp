@@ -87,13 +87,19 @@ __host__ __device__ inline TileLds tile_lds(int TU, int TX, bool f64) {
   return L;
 }
 
-// c ? v : 0 without control flow.  Written as a select, the compiler turns a load feeding it into
+// c ? v : 0 without control flow.  Written as a select, the compiler sinks a load feeding it into
 // a load under a divergent branch, and the end of that branch waits for every load in flight,
 // which serialises loads meant to overlap.  The mask here is opaque to the optimiser, so the load
 // (from a clamped, always valid address) stays unconditional and its wait moves to the first use.
+// By default the asm is not volatile, so the loads around it may be reordered freely; with ORD
+// it is volatile and also keeps the loads around it in program order (a masking step then waits
+// for its load before the next load is issued, but the compiler holds fewer loads in flight, which
+// measured faster where registers are short: the checkpointed solve and the nx = 128 solve).
+template <bool ORD = false>
 __device__ __forceinline__ double keep_if(bool c, double v) {
   int m = c ? -1 : 0;
-  asm volatile("" : "+v"(m));
+  if constexpr (ORD) asm volatile("" : "+v"(m));
+  else asm("" : "+v"(m));
   return __longlong_as_double(__double_as_longlong(v) & (long long)m);
 }
 

@@ -212,7 +212,7 @@ __device__ __forceinline__ double pick4(const double (&v)[16], int g, int qq) {
 // bit for bit (the U^Q tiles loaded from a stored block equal the ones the sweep leaves in LDS:
 // rounded to TF, zero below the diagonal and off the real rows, identity on the padding, whose
 // value never reaches a real entry).
-template <int TMAX, typename TF, typename TP, typename Dst>
+template <int TMAX, typename TF, typename TP, bool ORD = false, typename Dst>
 __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& d, int ka, int kb, Dst&& dst,
                                                   const TF* __restrict__ from, double* __restrict__ Vi,
                                                   unsigned char* lds, int& s_info) {
@@ -312,7 +312,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           for (int t = 0; t < 4; ++t) {
             const int ii = ib + 4 * t, ic = min(ii, nu - 1);
             const bool in = ii < nu && jb < nu;
-            h[t] = keep_if(in, 0.5 * (Rk[ic * nu + jc] + Rk[jc * nu + ic])) + (!in && ii == jb ? 1.0 : 0.0);
+            h[t] = keep_if<ORD>(in, 0.5 * (Rk[ic * nu + jc] + Rk[jc * nu + ic])) + (!in && ii == jb ? 1.0 : 0.0);
           }
         }
       } else if (bu) {
@@ -321,7 +321,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int ii = ib + 4 * t, ic = min(ii, nu - 1);
-            h[t] = keep_if(ii < nu && jb < nx, Sk[ic * nx + jc]);
+            h[t] = keep_if<ORD>(ii < nu && jb < nx, Sk[ic * nx + jc]);
           }
         }
       } else if (k > 0) {
@@ -330,7 +330,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
         for (int t = 0; t < 4; ++t) {
           const int ii = ib + 4 * t, ic = min(ii, nx - 1);
           const bool in = ii < nx && jb < nx;
-          h[t] = keep_if(in, 0.5 * (Qk[ic * nx + jc] + Qk[jc * nx + ic])) + (!in && ii == jb ? 1.0 : 0.0);
+          h[t] = keep_if<ORD>(in, 0.5 * (Qk[ic * nx + jc] + Qk[jc * nx + ic])) + (!in && ii == jb ? 1.0 : 0.0);
         }
       }
       return h;
@@ -399,7 +399,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int row = r0 + 16 * mp + MM<TP>::row(t, 0);
-          v[t] = keep_if(colok && row < nx, cb[min(row, nx - 1) * ldc]);
+          v[t] = keep_if<ORD>(colok && row < nx, cb[min(row, nx - 1) * ldc]);
         }
         return v;
       };
@@ -445,7 +445,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
       if (rhs && own) {
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
-        if (g == 0) rq[16 * a + c] = keep_if(ucol ? col < nu : (k > 0 && col < nx), base_raw) + part;
+        if (g == 0) rq[16 * a + c] = keep_if<ORD>(ucol ? col < nu : (k > 0 && col < nx), base_raw) + part;
       }
       // ---- G = [[R,S],[S^T,Q]] + W^T W in float64 (mixed: float32 layout -> float64 layout)
       if (own) {

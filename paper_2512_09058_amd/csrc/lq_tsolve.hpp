@@ -77,7 +77,7 @@ __device__ __forceinline__ int frag_col(const Lanes& L, int c) {
 
 // Load rows [0, nr) x columns [0, nc) of the row-major matrix M (leading dimension ld); entries
 // outside are zero (addresses are clamped, so every lane issues its loads).
-template <int R, int C, int CW, typename T>
+template <bool ORD, int R, int C, int CW, typename T>
 __device__ __forceinline__ void frag_load(Frag<R, C, CW>& f, const T* __restrict__ M, int nr, int nc, int ld,
                                           const Lanes& L, int W) {
 #pragma unroll
@@ -87,7 +87,7 @@ __device__ __forceinline__ void frag_load(Frag<R, C, CW>& f, const T* __restrict
     for (int c = 0; c < C; ++c) {
       const int j = frag_col<CW>(L, c);
       const double e = (double)M[(uint32_t)((r < nr ? r : nr - 1) * ld + (j < nc ? j : nc - 1))];
-      f.v[t][c] = keep_if(r < nr && j < nc, e);
+      f.v[t][c] = keep_if<ORD>(r < nr && j < nc, e);
     }
   }
 }
@@ -169,7 +169,7 @@ __device__ __forceinline__ void stream_sq(const double* __restrict__ M, int nr, 
     for (int c = 0; c < C; ++c) {
       const int j = frag_col<CW>(L, c);
       const double e = M[(uint32_t)(rc * nr + (j < nr ? j : nr - 1))];
-      v[c] = keep_if(r < nr && j < nr, e);
+      v[c] = keep_if<true>(r < nr && j < nr, e);  // (used at nx = 128 only)
       p = fma(v[c], x[j], p);
     }
     p = lane_sum<1, CW>(p);
@@ -208,10 +208,12 @@ __device__ __forceinline__ void tri_to_lds(const T* __restrict__ P, int n, doubl
       const int e = e0 + (int)threadIdx.x + c * NT;
       v[c] = (double)P[(uint32_t)(e < tot ? e : tot - 1)];
     }
+    // every lane stores (the ones past the end again the last entry, with its value), so that the
+    // loads are not sunk into a conditional store, where each would wait for itself
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int e = e0 + (int)threadIdx.x + c * NT;
-      if (e < tot) dst[e] = v[c];
+      dst[e < tot ? e : tot - 1] = v[c];
     }
   }
 }
@@ -220,7 +222,7 @@ __host__ __device__ constexpr int tri_chunk(int NP, int NT) {
   return (NP * (NP + 1) / 2 + NT - 1) / NT < 8 ? (NP * (NP + 1) / 2 + NT - 1) / NT : 8;
 }
 // A packed lower triangle of order n as a dense fragment (zero above the diagonal and outside).
-template <int R, int C, int CW, typename T>
+template <bool ORD, int R, int C, int CW, typename T>
 __device__ __forceinline__ void frag_load_tri(Frag<R, C, CW>& f, const T* __restrict__ P, int n, const Lanes& L,
                                               int W) {
 #pragma unroll
@@ -231,7 +233,7 @@ __device__ __forceinline__ void frag_load_tri(Frag<R, C, CW>& f, const T* __rest
     for (int c = 0; c < C; ++c) {
       const int j = frag_col<CW>(L, c);
       const double e = (double)P[(uint32_t)(rc * (rc + 1) / 2 + (j <= rc ? j : rc))];
-      f.v[t][c] = keep_if(r < n && j <= r, e);
+      f.v[t][c] = keep_if<ORD>(r < n && j <= r, e);
     }
   }
 }
@@ -300,6 +302,8 @@ __host__ __device__ constexpr int tsolve_lds_doubles(int W, int NXP, int NUP) {
 // the product type the factors were made with) when a pass first reaches it.
 template <int W, int NXP, int NUP, typename TF, int TMAX = 0, typename TP = TF>
 __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm) {
+  // loads masked with the ordered keep_if where registers are short (see keep_if)
+  constexpr bool ORD = TMAX > 0 || NXP > 64;
   typedef TS<W, NXP, NUP> S;
   static_assert(TMAX == 0 || TMAX == W, "the recomputation uses the solve's wavefronts");
   const Desc D = a.desc[b];
@@ -381,7 +385,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       auto dst = [&](int kk) -> TF* { return kk >= k0 && kk < k1 ? seg + (int64_t)(kk - k0) * fs : nullptr; };
       const TF* from = k1 < N ? Fi + ckpt_slot(k1, N, sc) * fs : nullptr;
       __syncthreads();
-      factor_tile_range<TMAX, TF, TP>(D, a.d, k0, k1, dst, from, nullptr, (unsigned char*)stg, s_rinfo);
+      factor_tile_range<TMAX, TF, TP, true>(D, a.d, k0, k1, dst, from, nullptr, (unsigned char*)stg, s_rinfo);
       seg0 = k0;
     }
   };
@@ -460,7 +464,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       // vectors, the other stage matrices into registers and the triangles into LDS
       Frag<(NXP <= 64 ? S::RXX : 1), S::XC, S::XW> fQ;
       if constexpr (NXP <= 64) {
-        if (k > 0) frag_load(fQ, Qk, nx, nx, nx, L, W);
+        if (k > 0) frag_load<ORD>(fQ, Qk, nx, nx, nx, L, W);
       }
       // vectors: unconditional loads from clamped indices (entries past nx / nu are never used)
       const int iu = ru ? tid : nu - 1, ix = rx ? tid : nx - 1;
@@ -468,7 +472,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       const double v_dr = (double)blk[off_dR(nx, nu) + iu];
       const double v_U0 = U[(int64_t)k * nu + iu];
       const double v_r = rhs_sign * r_src[(int64_t)k * nu + iu];
-      const double v_f = keep_if(has_f, f_src[(int64_t)k * nx + ix]);
+      const double v_f = keep_if<ORD>(has_f, f_src[(int64_t)k * nx + ix]);
       const double v_fl0 = flam[(int64_t)k * nx + ix];
       const double v_X0 = X[(int64_t)k * nx + ix];
       const double v_LM0 = LM[(int64_t)k * nx + ix];
@@ -478,11 +482,11 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       Frag<S::RXX, S::XC, S::XW> fA;
       Frag<S::RUU, 1, S::UW> fR;
       Frag<S::RUX, S::XC, S::XW> fS;
-      frag_load(fLS, blk + off_LS(nx, nu), nx, nu, nu, L, W);
-      frag_load(fA, Ak, nx, nx, nx, L, W);
-      frag_load(fB, Bk, nx, nu, nu, L, W);
-      frag_load(fR, R + (int64_t)k * nu * nu, nu, nu, nu, L, W);
-      if (Sm) frag_load(fS, Sm + (int64_t)k * nu * nx, nu, nx, nx, L, W);
+      frag_load<ORD>(fLS, blk + off_LS(nx, nu), nx, nu, nu, L, W);
+      frag_load<ORD>(fA, Ak, nx, nx, nx, L, W);
+      frag_load<ORD>(fB, Bk, nx, nu, nu, L, W);
+      frag_load<ORD>(fR, R + (int64_t)k * nu * nu, nu, nu, nu, L, W);
+      if (Sm) frag_load<ORD>(fS, Sm + (int64_t)k * nu * nx, nu, nx, nx, L, W);
       tri_to_lds<S::NT, tri_chunk(NUP, S::NT)>(blk, nu, LR);
       if constexpr (!LQREG) tri_to_lds<S::NT, tri_chunk(NXP, S::NT)>(blk1 + off_LQ(nx, nu), nx, LQ);
       // Q_k x_k (rows, into xs) and Q_k^T x_k (columns, hq) of the total iterate, k >= 1
@@ -509,7 +513,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       }
       // L^Q_{k+1} into registers (L^S_k is dead; the load completes behind the x-chain)
       Frag<(LQREG ? S::RXX : 1), S::XC, S::XW> fLQ;
-      if constexpr (LQREG) frag_load_tri(fLQ, blk1 + off_LQ(nx, nu), nx, L, W);
+      if constexpr (LQREG) frag_load_tri<ORD>(fLQ, blk1 + off_LQ(nx, nu), nx, L, W);
       __syncthreads();
       if (ru) us[tid] += colsum_total(pu, NUP, W, tid);
       __syncthreads();
@@ -675,16 +679,16 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       const TF* blk1 = blk_of(k + 1);
       const int iu = ru ? tid : nu - 1, ix = rx ? tid : nx - 1;
       const double v_fl = flam[(int64_t)k * nx + ix];
-      const double v_q = keep_if(k > 0, rhx[(int64_t)k * nx + ix]);
+      const double v_q = keep_if<ORD>(k > 0, rhx[(int64_t)k * nx + ix]);
       const double v_dr = (double)blk[off_dR(nx, nu) + iu];
       const double v_rv = rhu[(int64_t)k * nu + iu];
       Frag<S::RXU, 1, S::UW> fLS, fB;
       Frag<S::RXX, S::XC, S::XW> fA;
-      frag_load(fB, B + (int64_t)k * nx * nu, nx, nu, nu, L, W);
-      frag_load(fA, A + (int64_t)k * nx * nx, nx, nx, nx, L, W);
-      frag_load(fLS, blk + off_LS(nx, nu), nx, nu, nu, L, W);
+      frag_load<ORD>(fB, B + (int64_t)k * nx * nu, nx, nu, nu, L, W);
+      frag_load<ORD>(fA, A + (int64_t)k * nx * nx, nx, nx, nx, L, W);
+      frag_load<ORD>(fLS, blk + off_LS(nx, nu), nx, nu, nu, L, W);
       Frag<(LQREG ? S::RXX : 1), S::XC, S::XW> fLQ;
-      if constexpr (LQREG) frag_load_tri(fLQ, blk1 + off_LQ(nx, nu), nx, L, W);
+      if constexpr (LQREG) frag_load_tri<ORD>(fLQ, blk1 + off_LQ(nx, nu), nx, L, W);
       else tri_to_lds<S::NT, tri_chunk(NXP, S::NT)>(blk1 + off_LQ(nx, nu), nx, LQ);
       tri_to_lds<S::NT, tri_chunk(NUP, S::NT)>(blk, nu, LR);
       if (rx) fl[tid] = v_fl;

@@ -225,21 +225,21 @@ struct Seg {
 };
 
 // Coalesced store of the four instances' blocks of BLK elements from LDS to global memory
-// (instance i's block at i * istr + off).
+// (instance i's block at i * istr + off).  Every lane reads and stores: lanes past the last chunk or
+// instance repeat the last valid chunk with its own value, since a read feeding a conditional
+// store would be sunk into the condition and wait there.
 template <typename T, int BLK>
 __device__ __forceinline__ void store_blocks(T* gbase, int64_t istr, int64_t off, const T* lds, const Lane& L,
                                              int batch) {
   constexpr int W = chunk_w<T>(BLK, BLK, BLK, 0, BLK);
   using V = typename VecT<W * (int)sizeof(T)>::type;
   constexpr int CPI = BLK / W, TOT = 4 * CPI, NI = (TOT + 63) / 64;
+  const int gmax = min(3, batch - 1 - L.b0);  // last instance slot of the wavefront
 #pragma unroll
   for (int t = 0; t < NI; ++t) {
-    const int c = L.lane + 64 * t;
-    if (c < TOT) {
-      const int g = c / CPI, w = c % CPI;
-      if (L.b0 + g < batch)
-        *(V*)(gbase + (int64_t)(L.b0 + g) * istr + off + w * W) = *(const V*)(lds + g * BLK + w * W);
-    }
+    const int c = min(L.lane + 64 * t, TOT - 1);
+    const int g = min(c / CPI, gmax), w = c % CPI;
+    *(V*)(gbase + (int64_t)(L.b0 + g) * istr + off + w * W) = *(const V*)(lds + g * BLK + w * W);
   }
 }
 

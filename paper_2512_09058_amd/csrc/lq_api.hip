@@ -282,8 +282,11 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: hipGetDevice failed");
   }
-  hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device);
-  if (p->cu_count <= 0) p->cu_count = 256;
+  if (hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    p->cu_count = 0;
+  }
+  if (p->cu_count <= 0) p->cu_count = 256;  // (only sizes persistent grids)
   // longest instances first: serial Riccati operation count of each instance
   std::vector<int32_t> order(batch);
   std::vector<double> cost(batch);
@@ -302,7 +305,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   p->border_d = p->order_d + batch;
   if (hipMemcpy(p->desc_d, p->desc_h.data(), sizeof(Desc) * batch, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->order_d, order.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(p->desc_d);
+    (void)hipFree(p->desc_d);  // cleanup of a failed creation
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: descriptor upload failed");
   }
@@ -311,7 +314,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   if (lq::prepare_generic(false, p->lds_solve) != hipSuccess) {
     (void)hipGetLastError();
     const size_t need_solve = p->lds_solve;
-    hipFree(p->desc_d);
+    (void)hipFree(p->desc_d);  // cleanup of a failed creation
     delete p;
     return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve %zu bytes of LDS for the solve kernels", need_solve);
   }
@@ -376,7 +379,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     }
   }
   if ((p->variant == VAR_GENERIC && !p->can_generic) || (p->variant == VAR_TILE && !p->can_tile)) {
-    hipFree(p->desc_d);
+    (void)hipFree(p->desc_d);  // cleanup of a failed creation
     delete p;
     return fail(LQ_EUNSUPPORTED, "lq_plan_create: cannot reserve the LDS of the selected kernel");
   }
@@ -435,7 +438,7 @@ extern "C" int lq_plan_launch_groups(const lq_plan* p) {
 
 extern "C" void lq_plan_destroy(lq_plan* p) {
   if (!p) return;
-  if (p->desc_d) hipFree(p->desc_d);
+  if (p->desc_d) (void)hipFree(p->desc_d);
   delete p;
 }
 

@@ -156,6 +156,22 @@ def test_small_variant_config2_batch_and_tail():
     _check(rmx, sample=[0, 129])
 
 
+@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 10)])
+def test_config2_full_size_sampled(mode, max_it):
+    """Workload 2 at its full size (4096 instances, N = 50, nx = 12, nu = 4) in the launch the
+    benchmark times (one small-kernel launch per call): every instance's library residual and
+    status, and the oracle's residual and forward error on sampled instances, including every
+    instance that needed a second refinement iteration."""
+    print(f"case: workload 2 full size {mode}", flush=True)
+    b = synth.make_batch(2)
+    assert b.batch == 4096
+    res = run(b, mode, max_it=max_it)
+    assert res["plan"].variant == "small"
+    sample = sorted({0, 1, 2047, 4094, 4095} | {int(i) for i in np.flatnonzero(res["iters"] > 1)[:8]})
+    _check(res, sample=sample)
+    assert res["iters"].max() <= max(max_it, 0)
+
+
 def test_small_and_generic_agree():
     """Same instances through the specialised and the generic kernels (the generic one is forced
     by a ragged plan that appends one differently sized instance)."""

@@ -756,22 +756,28 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
   const int64_t fistr = (int64_t)(N + 1) * FS;
   double p2n = -s.rhox[(int64_t)N * NX + mi];
   if (xl) s.p2[(int64_t)N * NX + mi] = p2n;
-  // prologue: F_N in LDS; F_{N-1} and stage N-1 in flight; then the same code every stage, with
-  // clamped, unconditional prefetches (see fwd_res)
+  // prologue: F_N in LDS; stages N-1 and N-2 in flight in two register sets, used alternately, so
+  // that each stage's data is fetched two stages ahead (a wavefront running alone, as in the
+  // refinement tail, would otherwise wait for memory every stage); prefetch indices are clamped
+  // and unconditional (see fwd_res)
   {
     FSeg<NX, NU, TF> fa;
     fa.load(s.F, fistr, L, batch, N);
     fa.store(s.sF + (N & 1) * 4 * FS, L);
   }
-  FSeg<NX, NU, TF> fn;
-  StageData<NX, NU, HS, HF> dn;
-  fn.load(s.F, fistr, L, batch, N - 1);
-  dn.load(s.d, N, L, batch, N - 1, false);
   // (the lane's residual entry is read through a selected address: selecting between two loaded
   // values would wait for both right after they are issued)
-  double rho = *(isu ? s.rhou + (int64_t)(N - 1) * NU + ic : s.rhox + (int64_t)(N - 1) * NX + mi);
-  double fl = s.flam[(int64_t)(N - 1) * NX + mi];
-  for (int k = N - 1; k >= 0; --k) {
+  auto rho_at = [&](int k) { return *(isu ? s.rhou + (int64_t)k * NU + ic : s.rhox + (int64_t)k * NX + mi); };
+  FSeg<NX, NU, TF> fnA, fnB;
+  StageData<NX, NU, HS, HF> dnA, dnB;
+  const int kB = N > 1 ? N - 2 : 0;
+  fnA.load(s.F, fistr, L, batch, N - 1);
+  dnA.load(s.d, N, L, batch, N - 1, false);
+  double rhoA = rho_at(N - 1), flA = s.flam[(int64_t)(N - 1) * NX + mi];
+  fnB.load(s.F, fistr, L, batch, kB);
+  dnB.load(s.d, N, L, batch, kB, false);
+  double rhoB = rho_at(kB), flB = s.flam[(int64_t)kB * NX + mi];
+  auto step = [&](int k, FSeg<NX, NU, TF>& fn, StageData<NX, NU, HS, HF>& dn, double& rho_r, double& fl_r) {
     // the lane's L^Q_{k+1} coefficients (in LDS since the previous stage) read first, in one batch
     // (see fwd_res); the ones outside the triangle stay inside the block and are masked below
     const TF* Fk1 = s.sF + ((k + 1) & 1) * 4 * FS + g * FS;
@@ -783,14 +789,15 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
     }
     asm volatile("" ::: "memory");
     // F_k into slot k & 1 (held F_{k+2}, no longer needed), stage-k data into LDS, then stage
-    // k - 1 in flight
+    // k - 2 into the same registers
     fn.store(s.sF + (k & 1) * 4 * FS, L);
     dn.store(s.sC, s.sH, s.sRQ, s.sFv, L, false);
-    const int kp = k > 0 ? k - 1 : 0;
+    const double rho = rho_r, fl = fl_r;
+    const int kp = k > 1 ? k - 2 : 0;
     fn.load(s.F, fistr, L, batch, kp);
     dn.load(s.d, N, L, batch, kp, false);
-    const double rho_n = *(isu ? s.rhou + (int64_t)kp * NU + ic : s.rhox + (int64_t)kp * NX + mi);
-    const double fl_n = s.flam[(int64_t)kp * NX + mi];
+    rho_r = rho_at(kp);
+    fl_r = s.flam[(int64_t)kp * NX + mi];
     constexpr int RSP = SH::RSP;
     const TF* Fk = s.sF + (k & 1) * 4 * FS + g * FS;
     // input lanes: row ic of L^R (packed); state lanes: row mi of L^S (read in one batch)
@@ -832,8 +839,11 @@ __device__ void bwd_corr(const SolveCtx<NX, NU, TF, HS, HF>& s, bool act) {
     if (ul) s.rb2[(int64_t)k * NU + ic] = tq * dr;
     if (xl && k > 0) s.p2[(int64_t)k * NX + mi] = tq;
     p2n = tq;
-    rho = rho_n;
-    fl = fl_n;
+  };
+  for (int k = N - 1; k >= 0; k -= 2) {
+    step(k, fnA, dnA, rhoA, flA);
+    if (k == 0) break;
+    step(k - 1, fnB, dnB, rhoB, flB);
   }
 }
 

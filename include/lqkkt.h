@@ -161,8 +161,12 @@ int lq_plan_set_variant(lq_plan* plan, const char* name);
 /* Kernel-shape groups of the plan's current variant: a ragged batch on the "tile" variant (no
  * checkpoints) groups its instances by the kernel shapes sized for them (factor wavefronts,
  * padded solve sizes), each group one launch per call, heaviest group first, longest instance
- * first within a group (the per-bucket variants of the uneven-batch scheduling).  Returns the
- * group count (1: the whole batch in one launch per call), LQ_EINVAL for a NULL plan. */
+ * first within a group (the per-bucket variants of the uneven-batch scheduling).  The groups run
+ * at the same time: the first on the caller's stream, the others on streams the plan owns, forked
+ * from the caller's stream and joined back into it with events before the call returns (a graph
+ * capture of the caller's stream captures them).  Calls on such a plan must therefore not overlap
+ * each other.  Returns the group count (1: the whole batch in one launch per call), LQ_EINVAL for
+ * a NULL plan. */
 int lq_plan_launch_groups(const lq_plan* plan);
 
 /* Factor sweep (backward in time): for k = N-1..0 the stage products and the stage

@@ -128,6 +128,12 @@ struct lq_plan {
   };
   std::vector<Bucket> buckets;
   int32_t* border_d = nullptr;  // device: instance indices grouped by bucket, longest first within
+  // Streams on which the groups after the first run beside it, forked from and joined back into
+  // the caller's stream with events (capturable into a graph): ev[0] marks the fork, ev[i] the end
+  // of group i.  Empty when the plan launches one group (or could not create them: the groups then
+  // run one after another on the caller's stream).
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;
   size_t offCtr = 0;           // workspace: work counters of the persistent kernels
   int cu_count = 0;
   lq_launch launch = {128, 0, 0, 0};
@@ -376,6 +382,28 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
         (void)hipGetLastError();
         p->buckets.clear();
       }
+      // each group's persistent kernels take their own pair of work counters (2 + 2 i, 3 + 2 i)
+      if (2 * p->buckets.size() + 2 > 64) p->buckets.clear();
+      if (p->buckets.size() > 1) {
+        bool made = true;
+        for (size_t i = 0; i < p->buckets.size() && made; ++i) {
+          hipEvent_t e = nullptr;
+          made = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+          if (made) p->ev.push_back(e);
+          if (made && i > 0) {
+            hipStream_t st2 = nullptr;
+            made = hipStreamCreateWithFlags(&st2, hipStreamNonBlocking) == hipSuccess;
+            if (made) p->side.push_back(st2);
+          }
+        }
+        if (!made) {
+          (void)hipGetLastError();
+          for (hipStream_t x : p->side) (void)hipStreamDestroy(x);
+          for (hipEvent_t x : p->ev) (void)hipEventDestroy(x);
+          p->side.clear();
+          p->ev.clear();
+        }
+      }
     }
   }
   if ((p->variant == VAR_GENERIC && !p->can_generic) || (p->variant == VAR_TILE && !p->can_tile)) {
@@ -423,12 +451,38 @@ static lq::GenericLaunch generic_launch(const lq_plan* p, void* ws, bool factor)
   return c;
 }
 
-// Launch shape of one bucket's kernels: its slice of the grouped order, its persistent grid.
-static lq::GenericLaunch bucket_launch(const lq_plan* p, void* ws, bool factor, const lq_plan::Bucket& b) {
+// Launch shape of group i's kernels: its slice of the grouped order, its persistent grid, its own
+// work counters (the groups may run at the same time).
+static lq::GenericLaunch bucket_launch(const lq_plan* p, void* ws, bool factor, size_t i) {
+  const lq_plan::Bucket& b = p->buckets[i];
   lq::GenericLaunch c = generic_launch(p, ws, factor);
   c.order = p->border_d + b.off;
   c.grid = p->launch.persistent ? (factor ? b.grid_factor : b.grid_solve) : b.cnt;
+  if (c.counter) c.counter = (int32_t*)((char*)ws + p->offCtr) + 2 + 2 * (int)i + (factor ? 0 : 1);
   return c;
+}
+
+// Runs launch(i, stream) for every group: the first on the caller's stream, the others on the
+// plan's side streams after the fork point, all joined back before the caller's stream goes on.
+template <typename F>
+static hipError_t run_groups(const lq_plan* p, hipStream_t st, F&& launch) {
+  const size_t n = p->buckets.size();
+  hipError_t e = hipSuccess;
+  if (p->side.empty()) {
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) e = launch(i, st);
+    return e;
+  }
+  if ((e = hipEventRecord(p->ev[0], st)) != hipSuccess) return e;
+  if ((e = launch((size_t)0, st)) != hipSuccess) return e;
+  for (size_t i = 1; i < n; ++i) {
+    hipStream_t s2 = p->side[i - 1];
+    if ((e = hipStreamWaitEvent(s2, p->ev[0], 0)) != hipSuccess) return e;
+    if ((e = launch(i, s2)) != hipSuccess) return e;
+    if ((e = hipEventRecord(p->ev[i], s2)) != hipSuccess) return e;
+  }
+  for (size_t i = 1; i < n; ++i)
+    if ((e = hipStreamWaitEvent(st, p->ev[i], 0)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 extern "C" int lq_plan_launch_groups(const lq_plan* p) {
@@ -438,6 +492,8 @@ extern "C" int lq_plan_launch_groups(const lq_plan* p) {
 
 extern "C" void lq_plan_destroy(lq_plan* p) {
   if (!p) return;
+  for (hipStream_t x : p->side) (void)hipStreamDestroy(x);
+  for (hipEvent_t x : p->ev) (void)hipEventDestroy(x);
   if (p->desc_d) (void)hipFree(p->desc_d);
   delete p;
 }
@@ -503,12 +559,11 @@ extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* 
   if (p->variant == VAR_SMALL && lq::small_aligned(*d, ws))
     e = lq::launch_factor_small(p->mode, p->batch, p->N[0], p->nx[0], p->nu[0], *d, F, V, info, st);
   else if (p->variant == VAR_TILE && !p->buckets.empty()) {
-    e = hipSuccess;
-    for (const auto& b : p->buckets) {
-      e = lq::launch_factor_tile(p->mode, b.waves, p->desc_d, b.cnt, *d, F, V, info, b.lds_tile,
-                                 bucket_launch(p, ws, true, b), st);
-      if (e != hipSuccess) break;
-    }
+    e = run_groups(p, st, [&](size_t i, hipStream_t s2) {
+      const lq_plan::Bucket& b = p->buckets[i];
+      return lq::launch_factor_tile(p->mode, b.waves, p->desc_d, b.cnt, *d, F, V, info, b.lds_tile,
+                                    bucket_launch(p, ws, true, i), s2);
+    });
   } else if (p->variant == VAR_TILE)
     e = lq::launch_factor_tile(p->mode, p->tile_waves, p->desc_d, p->batch, *d, F, V, info, p->lds_tile,
                                generic_launch(p, ws, true), st);
@@ -543,13 +598,12 @@ static hipError_t launch_solve_plan(const lq_plan* p, const lq::SolveArgs& a, vo
   if (p->variant == VAR_TILE && p->ckpt)
     return lq::launch_solve_tckpt(p->ts_nxp, p->ts_nup, p->mode, a, p->lds_tckpt, c, st);
   if (p->variant == VAR_TILE && !p->buckets.empty()) {
-    for (const auto& b : p->buckets) {
+    return run_groups(p, st, [&](size_t i, hipStream_t s2) {
+      const lq_plan::Bucket& b = p->buckets[i];
       lq::SolveArgs ab = a;
       ab.batch = b.cnt;
-      const hipError_t e = lq::launch_solve_tsolve(b.nxp, b.nup, p->mode, ab, bucket_launch(p, ws, false, b), st);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+      return lq::launch_solve_tsolve(b.nxp, b.nup, p->mode, ab, bucket_launch(p, ws, false, i), s2);
+    });
   }
   if (p->variant == VAR_TILE && p->ts_nxp) return lq::launch_solve_tsolve(p->ts_nxp, p->ts_nup, p->mode, a, c, st);
   return lq::launch_solve_generic(p->mode, a, p->lds_solve, c, st);

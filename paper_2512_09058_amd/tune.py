@@ -67,22 +67,28 @@ def apply_cached(plan: api.Plan, path: Optional[str] = None) -> Optional[Dict]:
 
 
 def tune(plan: api.Plan, data: Dict[str, torch.Tensor], tol: float = 1e-10, max_it: int = 0, reps: int = 3,
-         path: Optional[str] = None, cands=None) -> Dict:
+         path: Optional[str] = None, cands=None, prune: float = 3.0) -> Dict:
+    """Times the candidates (best of reps runs after a first one); a candidate whose first run
+    already takes more than prune times the best time so far is not run again."""
     ws = plan.workspace()
     info = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
     rel = torch.zeros(plan.batch, dtype=torch.float64, device="cuda")
     x, u, lam = plan.empty_outputs()
     results = []
+    overall = float("inf")
     for c in (cands if cands is not None else candidates(plan)):
         _apply(plan, c)
         best = float("inf")
-        for _ in range(reps + 1):
+        for r in range(reps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             api.factor(plan, data, ws, info)
             api.solve(plan, data, ws, x, u, lam, rel, None, info, tol=tol, max_it=max_it)
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
+            if r == 0 and best > prune * overall:
+                break
+        overall = min(overall, best)
         results.append((best, c))
     results.sort(key=lambda r: r[0])
     choice = {"variant": results[0][1]["variant"], "launch": results[0][1]["launch"], "ms": results[0][0] * 1e3,

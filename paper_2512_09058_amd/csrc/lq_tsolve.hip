@@ -18,7 +18,7 @@ __global__ void k_reset_counter_ts(int32_t* c) {
 }
 
 // Wavefronts per workgroup for the padded state size.
-constexpr int ts_waves(int NXP) { return NXP <= 32 ? 2 : NXP <= 64 ? 4 : 8; }
+constexpr int ts_waves(int NXP) { return NXP <= 32 ? 2 : 8; }
 
 template <int NXP, int NUP, typename TF>
 const void* ts_kernel() {

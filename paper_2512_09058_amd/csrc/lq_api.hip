@@ -492,7 +492,11 @@ extern "C" int lq_plan_launch_groups(const lq_plan* p) {
 
 extern "C" void lq_plan_destroy(lq_plan* p) {
   if (!p) return;
-  for (hipStream_t x : p->side) (void)hipStreamDestroy(x);
+  // work of the plan's groups may still run on its streams: let it finish before they go
+  for (hipStream_t x : p->side) {
+    (void)hipStreamSynchronize(x);
+    (void)hipStreamDestroy(x);
+  }
   for (hipEvent_t x : p->ev) (void)hipEventDestroy(x);
   if (p->desc_d) (void)hipFree(p->desc_d);
   delete p;

@@ -42,11 +42,14 @@ namespace {
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
+// 1/sqrt(a): the hardware estimate (about 5e-8 relative) and NR Newton steps (two: 1 ulp; one:
+// about 4e-15, enough for factors that are rounded to float32 afterwards).
+template <int NR = 2>
 __device__ __forceinline__ double rsqrt_f64(double a) {
   double y = __builtin_amdgcn_rsq(a);
   const double h = 0.5 * a;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
+#pragma unroll
+  for (int s = 0; s < NR; ++s) y = y * fma(-h * y, y, 1.5);
   return y;
 }
 
@@ -95,7 +98,7 @@ __device__ __forceinline__ double rowmax(double v) {
 // Right-looking Cholesky of the row-distributed tile (lane i holds row i in h), pivot
 // columns 0..NCOL-1.  Returns 0, 1 (a pivot was not positive) or 2 (a pivot was not finite);
 // failed pivots are replaced by 1 so the sweep continues with finite numbers.
-template <int NUX, int NCOL>
+template <int NUX, int NCOL, int NR = 2>
 __device__ __forceinline__ int potrf_rows(double (&h)[NUX], double& mydinv, int i) {
   bool ok = true, fin = true;
 #pragma unroll
@@ -105,7 +108,7 @@ __device__ __forceinline__ int potrf_rows(double (&h)[NUX], double& mydinv, int 
     ok = ok && pos;
     fin = fin && isfinite(dj);
     dj = pos ? dj : 1.0;
-    const double inv = rsqrt_f64(dj);
+    const double inv = rsqrt_f64<NR>(dj);
     h[j] = (i == j) ? dj * inv : h[j] * inv;
     mydinv = (i == j) ? inv : mydinv;
 #pragma unroll
@@ -338,7 +341,7 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
       h[j] = v;
     }
     pn = d.q[(L.bb * (N + 1) + N) * NX + mi];
-    const int bad = potrf_rows<NUX, NUX>(h, mydinv, i);
+    const int bad = potrf_rows<NUX, NUX, sizeof(TF) == 4 ? 1 : 2>(h, mydinv, i);
     if (bad) code = bad == 2 ? LQ_INFO_NONFINITE : N + 1;
 #pragma unroll
     for (int j = 0; j < NUX; ++j) h[j] = rnd<TF>(h[j]);
@@ -428,8 +431,10 @@ __global__ void __launch_bounds__(64) k_factor_small(int batch, int N, lq_data d
     // of the unrolled Cholesky live across the stage loop and spills them)
     int io = i;
     asm volatile("" : "+v"(io));
-    if (k > 0) bad = potrf_rows<NUX, NUX>(h, mydinv, io);
-    else bad = potrf_rows<NUX, NU>(h, mydinv, io);
+    // (one Newton step for factors stored as float32, two for float64)
+    constexpr int NRS = sizeof(TF) == 4 ? 1 : 2;
+    if (k > 0) bad = potrf_rows<NUX, NUX, NRS>(h, mydinv, io);
+    else bad = potrf_rows<NUX, NU, NRS>(h, mydinv, io);
     if (bad && code == 0) code = bad == 2 ? LQ_INFO_NONFINITE : k + 1;
 #pragma unroll
     for (int j = 0; j < NUX; ++j) h[j] = rnd<TF>(h[j]);

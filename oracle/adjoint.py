@@ -35,6 +35,18 @@ def adjoint_grad(prob, gx, gu):
     return grads_from(prob, x, u, lam, xb, ub, lb), (x, u, lam), (xb, ub, lb)
 
 
+def adjoint_grad_banded(prob, gx, gu):
+    """``adjoint_grad`` with both solves (z and zbar) in banded storage, for horizons where the
+    dense K does not fit or is too slow; the same equations."""
+    K, b, L = kkt.assemble(prob)
+    z = kkt.banded_solve(K, b, L)
+    x, u, lam = kkt.split(z, L)
+    g = kkt.join(np.asarray(gx, np.float64), np.asarray(gu, np.float64), np.zeros_like(lam), L)
+    zb = kkt.banded_solve(K, g, L)
+    xb, ub, lb = kkt.split(zb, L)
+    return grads_from(prob, x, u, lam, xb, ub, lb), (x, u, lam), (xb, ub, lb)
+
+
 def grads_from(prob, x, u, lam, xb, ub, lb):
     N, nx, nu = prob.N, prob.nx, prob.nu
     xs = np.vstack([prob.x0[None, :], x])           # x_0 .. x_N

@@ -137,23 +137,28 @@ def _interleave_perm(L):
     return np.asarray(idx)
 
 
-def solve_banded(prob):
-    """Same system as ``solve_dense`` in banded storage (for horizons where dense K does not fit).
+def banded_solve(K, rhs, L):
+    """Solve K z = rhs for the assembled K of one instance in banded storage.
 
     The unknowns are permuted stage-interleaved so that K has bandwidth below
     2 (nu + 2 nx); the banded matrix is solved by LAPACK's banded LU.
     """
-    K, b, L = assemble(prob)
     perm = _interleave_perm(L)
     Kp = K[perm][:, perm].tocoo()
     lo = int(max(0, (Kp.row - Kp.col).max()))
     up = int(max(0, (Kp.col - Kp.row).max()))
     ab = np.zeros((lo + up + 1, L.n))
     ab[up + Kp.row - Kp.col, Kp.col] = Kp.data
-    zp = scipy.linalg.solve_banded((lo, up), ab, b[perm], check_finite=True)
+    zp = scipy.linalg.solve_banded((lo, up), ab, rhs[perm], check_finite=True)
     z = np.empty(L.n)
     z[perm] = zp
-    return split(z, L)
+    return z
+
+
+def solve_banded(prob):
+    """Same system as ``solve_dense`` in banded storage (for horizons where dense K does not fit)."""
+    K, b, L = assemble(prob)
+    return split(banded_solve(K, b, L), L)
 
 
 def residual(prob, x, u, lam):

@@ -94,6 +94,55 @@ def test_residual_sees_each_block():
     assert np.abs(rho[others]).max() < 1e-12
 
 
+ERRGOLD = os.path.join(os.path.dirname(__file__), "golden", "error_measures.json")
+
+
+def test_error_measures_hand_values():
+    """Backward error, relative residual and dynamics violation of perturbed iterates of the hand
+    examples against values computed by hand in exact fractions (tests/golden/error_measures.json)."""
+    exs = {e["name"]: e for e in json.load(open(GOLD))["examples"]}
+    for case in json.load(open(ERRGOLD))["cases"]:
+        p = _prob_from_json(exs[case["example"]])
+        it = case["iterate"]
+        x, u, lam = _frac(it["x"]), _frac(it["u"]), _frac(it["lam"])
+        assert kkt.backward_error(p, x, u, lam) == pytest.approx(float(Fraction(case["backward_error"])), rel=1e-15)
+        assert kkt.residual(p, x, u, lam)[1] == pytest.approx(float(Fraction(case["rel_res"])), rel=1e-15)
+        assert kkt.dynamics_violation(p, x, u) == pytest.approx(float(Fraction(case["dynamics_violation"])),
+                                                                abs=1e-15)
+
+
+def test_error_measures_bound_each_other():
+    """For any iterate the backward error is at most the relative residual (its denominator is
+    larger), and both vanish at the exact solution; the dynamics violation is at most the
+    residual's largest dynamics row."""
+    p = synth.random_problem(31, 7, 4, 3)
+    x, u, lam = kkt.solve_dense(p)
+    assert kkt.backward_error(p, x, u, lam) < 1e-15
+    assert kkt.dynamics_violation(p, x, u) < 1e-13
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        xp = x + 1e-3 * rng.standard_normal(x.shape)
+        up = u + 1e-3 * rng.standard_normal(u.shape)
+        rho, rel = kkt.residual(p, xp, up, lam)
+        be = kkt.backward_error(p, xp, up, lam)
+        _, b, L = kkt.assemble(p)
+        assert 0 < be <= rel
+        dyn = max(np.abs(rho[L.lam(k)]).max() for k in range(p.N))
+        assert kkt.dynamics_violation(p, xp, up) == pytest.approx(dyn, rel=1e-12)
+
+
+def test_banded_adjoint_matches_dense():
+    """The banded adjoint route (used at horizons where the dense one is too slow) gives the dense
+    route's gradients, which are pinned to finite differences below."""
+    p = synth.random_problem(41, 9, 5, 3)
+    x, u, _ = kkt.solve_dense(p)
+    _, gx, gu = adjoint.quad_loss(x, u)
+    gd, _, _ = adjoint.adjoint_grad(p, gx, gu)
+    gb, _, _ = adjoint.adjoint_grad_banded(p, gx, gu)
+    for k in gd:
+        assert np.abs(gd[k] - gb[k]).max() <= 1e-12 * max(1.0, np.abs(gd[k]).max()), k
+
+
 @pytest.mark.parametrize("a,b,q,r", [(0.9, 0.5, 1.0, 0.1), (1.2, 1.0, 2.0, 0.5), (0.3, 2.0, 0.7, 3.0)])
 def test_scalar_dare_closed_form(a, b, q, r):
     N = 1000
@@ -236,6 +285,10 @@ MUTATIONS = [
     (riccati, "recursion", "Rhat = sym(prob.R[k]) + B.T @ Pn @ B", "Rhat = sym(prob.R[k]) + B.T @ B"),
     (riccati, "solve", "lam[k] = rec[\"P\"][k + 1] @ xn + rec[\"p\"][k + 1]", "lam[k] = rec[\"P\"][k] @ xn + rec[\"p\"][k + 1]"),
     (condense, "solve", "rv[0:nu] += S[0] @ prob.x0", "rv[0:nu] -= S[0] @ prob.x0"),
+    (kkt, "backward_error", "(knorm * np.abs(z).max() + np.abs(b).max())", "(knorm * np.abs(z).max())"),
+    (kkt, "backward_error", "knorm = np.abs(K).sum(axis=1).max()", "knorm = np.abs(K).max()"),
+    (kkt, "dynamics_violation", "fk - xs[k + 1]", "fk - xs[k]"),
+    (kkt, "dynamics_violation", "prob.B[k] @ u[k]", "prob.B[k] @ u[max(k - 1, 0)]"),
 ]
 
 
@@ -244,6 +297,13 @@ def test_planted_mistake_is_caught(mod, fname, old, new, monkeypatch):
     bad = _mutant(mod, fname, old, new)
     monkeypatch.setattr(mod, fname, bad)
     caught = False
+    if fname in ("backward_error", "dynamics_violation"):
+        try:
+            test_error_measures_hand_values()
+        except AssertionError:
+            caught = True
+        assert caught, f"mutation in {mod.__name__}.{fname} not detected"
+        return
     try:
         test_hand_examples("dense" if mod is kkt else ("riccati" if mod is riccati else "condense"))
     except AssertionError:

@@ -17,8 +17,11 @@ Contents (each function cites the passage of the paper it follows):
 * ``adjoint``  -- gradients of a loss of the solution through the KKT system,
                   and central finite differences.
 * ``closed``   -- closed forms (scalar discrete algebraic Riccati equation).
+* ``blocktri`` -- symmetric positive definite block-tridiagonal systems: dense definition, the
+                  cyclic-reduction factor as the Cholesky factor of the valuation-ordered
+                  matrix, the written-out CR and PCR recursions, preconditioned CG.
 
 All arithmetic is float64 with numpy / scipy (LAPACK).  Nothing here is blocked,
 fused or reordered beyond the definitions.
 """
-from . import adjoint, closed, condense, kkt, riccati  # noqa: F401
+from . import adjoint, blocktri, closed, condense, kkt, riccati  # noqa: F401

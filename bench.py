@@ -46,21 +46,74 @@ def algorithmic_bytes_factor(batch, N, nx, nu, fbytes):
     return batch * N * (8 * data + fbytes * fac + 8 * (nu + nx))
 
 
-def algorithmic_bytes_solve(N, nx, nu, fbytes, iters):
-    """Minimum HBM bytes of one solve launch of this design, summed over instances (iters = the
-    per-instance refinement iterations).  Per stage:
-      forward+residual pass: read factors, A, B, Q, R, q, r, sweep vectors (+ old iterate and
-        flam in correction passes); write x, u, lam (+ the residual when another iteration follows);
-      backward correction pass: read factors, A, B, the stored residual; write the sweep vectors."""
+def algorithmic_bytes_solve(N, nx, nu, fbytes, iters=None):
+    """Algorithmic HBM bytes of one solve launch per instance: ONE forward rollout with the float64
+    KKT residual fused in (read the factors in their storage precision, the stage data A, B, Q_k,
+    R, q_k, r and the sweep vectors rbar_k, p_k; write x, u, lam).  Refinement passes are
+    implementation bytes of this design, counted by `refinement_bytes`, never here."""
+    data, fac = stage_sizes(nx, nu)
+    z = 2 * nx + nu
+    n_inst = 1 if iters is None else len(iters)
+    return int(n_inst * N * (8 * data + fbytes * fac + 8 * (nu + nx) + 8 * z))
+
+
+def refinement_bytes(N, nx, nu, fbytes, iters):
+    """Implementation bytes the refinement adds to a solve launch, summed over instances (iters =
+    per-instance refinement iterations).  Per stage and iteration: the residual store of the pass
+    before it; a backward correction pass (read factors, A, B and the stored residual, write the
+    correction sweep vectors); a forward correction pass with the residual (read factors, stage
+    data, sweep vectors, the iterate and the dynamics residual; write the iterate)."""
     data, fac = stage_sizes(nx, nu)
     z = 2 * nx + nu
     total = 0
     for it in np.asarray(iters, dtype=np.int64):
-        fwd0 = 8 * data + fbytes * fac + 8 * (nu + nx) + 8 * z + (8 * z if it > 0 else 0)
+        if it <= 0:
+            continue
         bwd = fbytes * fac + 8 * (nx * nx + nx * nu) + 8 * z + 8 * (nu + nx)
         fwd1 = 8 * data + fbytes * fac + 8 * (nu + nx) + 8 * nx + 16 * z
-        total += fwd0 + it * (bwd + fwd1) + max(it - 1, 0) * 8 * z
+        total += 8 * z + it * (bwd + fwd1) + (it - 1) * 8 * z
     return int(total) * N
+
+
+def measure_copy_bandwidth():
+    """HBM bandwidth of a plain device-to-device copy of 1 GiB (read + write bytes / time, median of
+    five copies timed with events): the measured peak the roofline fraction is also given against."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2 * n * 8 / (float(np.median(ts)) * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def hbm_roofline(kernel, nbytes, ms, copy_gbs, traffic=None, extra=None):
+    a = nbytes / (ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "kernel": kernel, "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": a / HBM_PEAK_GBS, "traffic": traffic, "peak_measured_copy": copy_gbs,
+         "frac_measured_copy": a / copy_gbs if copy_gbs else None,
+         "algorithmic_bytes_per_launch": nbytes, "ms_per_launch": ms}
+    if extra:
+        r.update(extra)
+    return r
 
 
 def profiled_traffic(kernel):
@@ -105,7 +158,7 @@ def cpu_baseline(sample=2048, workers=None):
         times = pool.map(oracle_worker, jobs)
     n = per * workers
     t = max(times)
-    return {"value": n / t, "unit": "solves/s", "cores": workers, "kind": "oracle",
+    return {"value": n / t, "unit": "solves/s", "cores": workers, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n} instances of the workload (same generator), textbook Riccati route "
                       f"(numpy float64, 1 BLAS thread per process), {workers} processes, slowest {t:.1f} s"}
 
@@ -284,7 +337,7 @@ def _cpu_uneven(insts, sols, per_bucket=None, workers=16):
             mode: {"oracle_rel_res": max(kkt.residual(insts[i], *sols[mode][i])[1] for i in pick),
                    "fwd_err_vs_oracle": max(_fwd_err(sols[mode][i], ref[i]) for i in pick)}
             for mode in sols}
-    return {"value": len(sample) / t, "unit": "solves/s", "cores": workers, "kind": "oracle",
+    return {"value": len(sample) / t, "unit": "solves/s", "cores": workers, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{len(sample)} instances ({per_bucket or 'all'} per nx bucket), textbook Riccati route (numpy float64, "
                       f"1 BLAS thread per process), {workers} processes, slowest {t:.1f} s",
             "gpu_vs_oracle_sampled": check}
@@ -361,7 +414,7 @@ def _cpu_uniform(cfg, per, workers, adj, what):
     with ctx.Pool(workers) as pool:
         times = pool.map(_oracle_time_worker, [(cfg, w * per, per, adj) for w in range(workers)])
     n, t = per * workers, max(times)
-    return {"value": n / t, "unit": "solves/s", "cores": workers, "kind": "oracle",
+    return {"value": n / t, "unit": "solves/s", "cores": workers, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n} instances of the workload, {what} (numpy float64, 1 BLAS thread per process), "
                       f"{workers} processes, slowest {t:.1f} s"}
 
@@ -534,6 +587,88 @@ def bench_adjoint(args):
     print(json.dumps(out))
 
 
+def bench_single(args):
+    """The single-problem workload (N = 20, nx = 4, nu = 2, float64): latency of one factor + solve
+    on the GPU (each call timed with events, and as a replayed hipGraph), beside the oracle's
+    dense KKT solve and textbook Riccati route on one host core, with the GPU result checked
+    against the oracle."""
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    from oracle import kkt, riccati
+    p = synth.make_instance(1, 0)
+    plan = L.Plan([p.N], [p.nx], [p.nu], mode="f64")
+    data = L.pack([p])
+    ws = plan.workspace()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rel = torch.zeros(1, dtype=torch.float64, device="cuda")
+    x, u, lam = plan.empty_outputs()
+    stream = torch.cuda.current_stream()
+    reps = max(args.steps, 200)
+    for _ in range(args.warmup + 10):
+        L.factor(plan, data, ws, info, stream=stream)
+        L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=0, stream=stream)
+    torch.cuda.synchronize()
+    us = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        L.factor(plan, data, ws, info, stream=stream)
+        L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=0, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us.append(1e3 * e0.elapsed_time(e1))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.factor(plan, data, ws, info, stream=stream)
+        L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=0, stream=stream)
+        torch.cuda.synchronize()
+    wall_us = 1e6 * (time.perf_counter() - t0) / reps
+    g = L.api.capture(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_us = 1e6 * (time.perf_counter() - t0) / reps
+    sol = [L.unpack(plan, n, t_, 0) for n, t_ in (("x", x), ("u", u), ("lam", lam))]
+    ref = kkt.solve_dense(p)
+    out_cpu = None
+    if not args.no_cpu:
+        for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[v] = "1"
+        tc = {}
+        for name, fn in (("dense_kkt", kkt.solve_dense), ("textbook_riccati", riccati.solve)):
+            n, t0 = 0, time.perf_counter()
+            while time.perf_counter() - t0 < 2.0:
+                fn(p)
+                n += 1
+            tc[name] = 1e6 * (time.perf_counter() - t0) / n
+        out_cpu = {"value": tc["textbook_riccati"], "unit": "us/solve", "cores": 1, "kind": "oracle",
+                   "cpu_model": cpu_model(),
+                   "sample": "the one instance, solved repeatedly for 2 s per route in this process "
+                             "(numpy float64; BLAS threads as numpy was loaded)",
+                   "dense_kkt_us": tc["dense_kkt"], "textbook_riccati_us": tc["textbook_riccati"]}
+    med = float(np.median(us))
+    out = {"metric": "us per LQ KKT solve, single problem N=20 nx=4 nu=2, FP64", "value": med, "unit": "us/solve",
+           "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": med * 1e-3,
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generators of the workload)",
+           "config": {"workload": "single LQ problem, N=20, nx=4, nu=2, FP64 factor + solve", "batch": 1,
+                      "variant": plan.variant},
+           "gpu_event_us_median": med, "gpu_event_us_min": float(np.min(us)),
+           "host_wall_us_with_sync": wall_us, "graph_replay_us": graph_us,
+           "rel_res": float(rel.item()), "info": int(info.item()),
+           "oracle_rel_res_of_gpu_solution": float(kkt.residual(p, *sol)[1]),
+           "fwd_err_vs_oracle": _fwd_err(sol, ref),
+           "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": "us", "frac": None,
+                        "traffic": None},
+           "cpu_baseline": out_cpu}
+    print(f"[bench] single: GPU {med:.1f} us (events), {wall_us:.1f} us host wall with sync, graph "
+          f"{graph_us:.1f} us", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -545,7 +680,8 @@ def main():
     ap.add_argument("--distinct", type=int, default=0,
                     help="large / adjoint workloads: generate only this many distinct instances and repeat them "
                          "(0: all distinct)")
-    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024"], default="batch4096",
+    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20"],
+                    default="batch4096",
                     help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
                          "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -580,6 +716,8 @@ def main():
         return bench_large(args)
     if args.workload == "adjoint1024":
         return bench_adjoint(args)
+    if args.workload == "single20":
+        return bench_single(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)
@@ -608,7 +746,9 @@ def main():
                       for i in (0, 1, 777, 2048, 4095))
             for mode, r in res.items()}
 
-    # roofline of the dominant kernel of the reported (mixed) path
+    # roofline of the dominant kernel of the reported (mixed) path: algorithmic bytes are one
+    # factor sweep / one forward + residual pass; the refinement passes are reported apart
+    copy_gbs = measure_copy_bandwidth()
     it_mean = float(np.mean(m["iters"]))
     names = {"factor": f"k_factor_small<{NX}, {NU}, float, float, false, false>",
              "solve": f"k_solve_small<{NX}, {NU}, float, false, false>"}
@@ -616,13 +756,21 @@ def main():
             "solve": (m["ms_solve"], algorithmic_bytes_solve(N, NX, NU, 4, m["iters"]))}
     dom = max(kern, key=lambda k: kern[k][0])
     ms, by = kern[dom]
-    achieved = by / (ms * 1e-3) / 1e9
     tr = profiled_traffic(names[dom]) if m["plan"].variant == "small" else None
+    ref_b = refinement_bytes(N, NX, NU, 4, m["iters"])
     f64k = {"factor": {"ms": f["ms_factor"], "algorithmic_bytes": algorithmic_bytes_factor(BATCH, N, NX, NU, 8)},
             "solve": {"ms": f["ms_solve"], "algorithmic_bytes": algorithmic_bytes_solve(N, NX, NU, 8, f["iters"])}}
     for v in f64k.values():
         v["GBps"] = v["algorithmic_bytes"] / (v["ms"] * 1e-3) / 1e9
     mxk = {k: {"ms": v[0], "algorithmic_bytes": v[1], "GBps": v[1] / (v[0] * 1e-3) / 1e9} for k, v in kern.items()}
+    mxk["solve"]["refinement_implementation_bytes"] = ref_b
+    mxk["solve"]["GBps_with_refinement_bytes"] = (kern["solve"][1] + ref_b) / (m["ms_solve"] * 1e-3) / 1e9
+    # the whole step against the fused ideal (inputs read once, x, u, lam written once)
+    data_b, _ = stage_sizes(NX, NU)
+    ideal = BATCH * N * (8 * data_b + 8 * (2 * NX + NU))
+    step_vs_ideal = {"ideal_bytes": ideal, "ideal_ms_at_peak": ideal / (HBM_PEAK_GBS * 1e9) * 1e3,
+                     "mixed_frac": ideal / (m["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "fp64_frac": ideal / (f["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out = {
         "metric": METRIC,
         "value": BATCH / (m["ms_per_step"] * 1e-3),
@@ -645,9 +793,8 @@ def main():
                   "kernels": mxk},
         "mixed_over_fp64": f["ms_per_step"] / m["ms_per_step"],
         "equal_residual_ok": bool(ok),
-        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "algorithmic_bytes_per_launch": by, "ms_per_launch": ms},
+        "step_vs_fused_ideal": step_vs_ideal,
+        "roofline": hbm_roofline(names[dom], by, ms, copy_gbs, tr),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

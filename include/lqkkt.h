@@ -169,10 +169,19 @@ int lq_plan_set_variant(lq_plan* plan, const char* name);
  * a NULL plan. */
 int lq_plan_launch_groups(const lq_plan* plan);
 
-/* Factor sweep (backward in time): for k = N-1..0 the stage products and the stage
- * Cholesky, storing L^R_k, L^S_k, L^Q_k in `workspace`; also the backward sweep of the
- * right-hand side (q, r, f) that lq_solve continues.  `info` (device, int32[B]) receives the
- * per-instance factor status.  lq_solve must be called with the same `data`. */
+/* Factor sweep (backward in time), paper Alg. "factor-block-column-riccati" with one interval
+ * (its stage step: trmm V_k = [B_k^T; A_k^T] L^Q_{k+1}, syrk Hhat_k = [[R_k,S_k],[S_k^T,Q_k]] +
+ * V_k V_k^T, potrf chol(Hhat_k) = [[L^R_k,0],[L^S_k,L^Q_k]]; P_k = L^Q_k L^Q_k^T is the cost-to-go
+ * of eq. riccati-recursion-P): for k = N-1..0, starting from L^Q_N = chol(Q_N), storing L^R_k,
+ * L^S_k, L^Q_k (lower triangles only, eq. redundant-fact) in `workspace`; also the backward
+ * substitution of the right-hand side (q, r, f) of eq. opt-cond-ocp-eq, which lq_solve continues.
+ *   workspace  device, lq_plan_workspace_bytes(plan) bytes, 256-byte aligned, caller-owned; its
+ *              contents are valid for lq_solve / lq_solve_backward with the same plan and data.
+ *   info       device int32[B], written: 0, or k+1 for the first stage k (met going backward)
+ *              whose matrix is not positive definite (the sweep continues with a unit pivot).
+ * Returns LQ_EINVAL for a NULL plan / data / required array / workspace / info, a misaligned
+ * workspace or a device other than the plan's; LQ_EHIP if the launch fails.
+ * lq_solve must be called with the same `data`. */
 int lq_factor(const lq_plan* plan, const lq_data* data, void* workspace, int32_t* info,
               hipStream_t stream);
 
@@ -187,7 +196,10 @@ int lq_solve(const lq_plan* plan, const lq_data* data, void* workspace, const lq
              double* x, double* u, double* lam, double* rel_res, int32_t* iters, int32_t* info,
              hipStream_t stream);
 
-/* Adjoint of lq_solve.  Given the solution (x, u, lam) from lq_solve with the same plan,
+/* Adjoint of lq_solve: the derivative of the solution of eq. opt-cond-ocp-eq with respect to the
+ * problem data of eq. ocp-eq, by the transposed KKT solve (K is symmetric, so the same stored
+ * factors of Alg. "factor-block-column-riccati" solve it).  Given the solution (x, u, lam) from
+ * lq_solve with the same plan,
  * data and factored workspace, and upstream gradients gx = dl/dx_k (k = 1..N, layout of x)
  * and gu = dl/du_k (layout of u), solves K zbar = (gu, gx, 0) with the stored factors (K is
  * symmetric), refined like lq_solve, and writes
@@ -196,8 +208,10 @@ int lq_solve(const lq_plan* plan, const lq_data* data, void* workspace, const lq
  *   gS_k = -(ubar_k x_k^T + u_k xbar_k^T)          gq_k = -xbar_k (gq_0 = 0), gr_k = -ubar_k
  *   gf_k = -lambar_k                               gx0 = -(A_0^T lambar_0 + S_0^T ubar_0)
  * with x_0 = x_init and xbar_0 = 0 (sym(M) = (M + M^T)/2, since Q and R enter through their
- * symmetric parts).  Gradient arrays use the input layouts; gS and gf may be NULL.
- * rel_res / iters / info as in lq_solve, for the adjoint system. */
+ * symmetric parts).  Gradient arrays (device float64, caller-owned, written in full) use the
+ * input layouts; gS and gf may be NULL.  The adjoint solution zbar is kept in `workspace`.
+ * rel_res / iters / info as in lq_solve, for the adjoint system; returns LQ_EINVAL for a missing
+ * required pointer, LQ_EHIP if a launch fails. */
 int lq_solve_backward(const lq_plan* plan, const lq_data* data, void* workspace,
                       const lq_solve_opts* opts, const double* x, const double* u,
                       const double* lam, const double* gx, const double* gu, double* gA,

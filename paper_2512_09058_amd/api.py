@@ -193,7 +193,11 @@ def capture(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, l
             info=None, tol: float = 1e-10, max_it: int = 0, check_res: bool = True, warmup: int = 1):
     """Capture lq_factor + lq_solve on a side stream into a HIP graph (torch.cuda.CUDAGraph);
     replay() re-runs the whole sequence on the captured buffers.  The calls only enqueue kernels
-    (work counters are reset by a kernel, not a memset), so nothing else lands in the graph."""
+    (work counters are reset by a kernel, not a memset), so nothing else lands in the graph.
+
+    The graph's kernels read the plan's device tables and the given buffers by address, so the
+    returned graph holds references to all of them (`g.lq_keepalive`): the plan and the buffers
+    live at least as long as the graph."""
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -209,4 +213,5 @@ def capture(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, l
         factor(plan, data, ws, info, stream=st)
         solve(plan, data, ws, x, u, lam, rel_res, iters, info, tol=tol, max_it=max_it, check_res=check_res,
               stream=st)
+    g.lq_keepalive = (plan, data, ws, x, u, lam, rel_res, iters, info)
     return g

@@ -100,21 +100,22 @@ __device__ __forceinline__ double rowmax(double v) {
 // failed pivots are replaced by 1 so the sweep continues with finite numbers.
 template <int NUX, int NCOL, int NR = 2>
 __device__ __forceinline__ int potrf_rows(double (&h)[NUX], double& mydinv, int i) {
-  bool ok = true, fin = true;
+  // the first failing pivot classifies the stage: finite and not positive (1) or not finite (2);
+  // what the replaced pivot does to the later pivots of the stage does not change that
+  int kind = 0;
 #pragma unroll
   for (int j = 0; j < NCOL; ++j) {
     double dj = bc(h[j], j);
-    const bool pos = dj > 0.0;
-    ok = ok && pos;
-    fin = fin && isfinite(dj);
-    dj = pos ? dj : 1.0;
+    const bool good = dj > 0.0 && dj <= 1.7976931348623157e308;
+    kind = kind ? kind : (good ? 0 : (isfinite(dj) ? 1 : 2));
+    dj = good ? dj : 1.0;
     const double inv = rsqrt_f64<NR>(dj);
     h[j] = (i == j) ? dj * inv : h[j] * inv;
     mydinv = (i == j) ? inv : mydinv;
 #pragma unroll
     for (int kk = j + 1; kk < NCOL; ++kk) h[kk] = fma(-h[j], bc(h[j], kk), h[kk]);
   }
-  return ok ? 0 : (fin ? 1 : 2);
+  return kind;
 }
 
 template <typename T>

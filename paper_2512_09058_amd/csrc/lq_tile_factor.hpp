@@ -160,24 +160,24 @@ __device__ __forceinline__ typename MM<TP>::V tmm(typename MM<TP>::V acc, const 
 }
 
 // Right-looking Cholesky of a 16x16 tile held one row per lane (lane c of each 16-lane row:
-// row c in h).  Returns 0, 1 (a pivot was not positive) or 2 (not finite); failed pivots are
-// replaced by 1.  On return h[0..c] is row c of L and dinv = 1 / L[c][c].
+// row c in h).  Returns 0, or for the first failing pivot 1 (finite, not positive) or 2 (not
+// finite); failed pivots are replaced by 1, so later pivots of a failed tile are meaningless.  On return h[0..c] is row c of L and dinv = 1 / L[c][c].
 __device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c) {
-  bool ok = true, fin = true;
+  // the first failing pivot classifies the tile (see the comment above)
+  int kind = 0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     double dj = bc(h[j], j);
-    const bool pos = dj > 0.0;
-    ok = ok && pos;
-    fin = fin && isfinite(dj);
-    dj = pos ? dj : 1.0;
+    const bool good = dj > 0.0 && dj <= 1.7976931348623157e308;
+    kind = kind ? kind : (good ? 0 : (isfinite(dj) ? 1 : 2));
+    dj = good ? dj : 1.0;
     const double inv = rsqrt_f64(dj);
     h[j] = (c == j) ? dj * inv : h[j] * inv;
     dinv = (c == j) ? inv : dinv;
 #pragma unroll
     for (int kk = j + 1; kk < 16; ++kk) h[kk] = fma(-h[j], bc(h[j], kk), h[kk]);
   }
-  return ok ? 0 : (fin ? 1 : 2);
+  return kind;
 }
 
 // Columns 4g .. 4g+3 of row c of X = L^{-1} in lane c of 16-lane row g, from L held one row per

@@ -9,6 +9,7 @@ from .problems import (  # noqa: F401
     SEED_ROOT,
     config_sizes,
     make_batch,
+    make_batch_parallel,
     make_instance,
     make_ragged,
     random_problem,

@@ -26,6 +26,7 @@ A (all k), B, M (for Q, k = 0..N), R, q (k = 0..N), r, x0.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -105,10 +106,13 @@ def _rng(cfg: int, i: int) -> np.random.Generator:
     return np.random.default_rng(np.random.SeedSequence([SEED_ROOT, cfg, 1, i]))
 
 
-def _haar(rng, n):
-    g = rng.standard_normal((n, n))
+def _haar(rng, n, count):
+    """`count` Haar-orthogonal n x n matrices: QR of N(0,1) matrices with the signs of diag(R)
+    moved into Q.  The normals are drawn in one call (the same stream as `count` successive
+    n x n draws) and factored as a stack (the same LAPACK routine per matrix)."""
+    g = rng.standard_normal((count, n, n))
     qm, rm = np.linalg.qr(g)
-    return qm * np.sign(np.diag(rm))[None, :]
+    return qm * np.sign(np.diagonal(rm, axis1=-2, axis2=-1))[:, None, :]
 
 
 def config_sizes(cfg: int):
@@ -131,7 +135,7 @@ def _draw(rng, cfg, N, nx, nu, N_override=None):
         Q = _sym(M @ np.swapaxes(M, -1, -2)) + 0.1 * eye_x
         R = 0.1 * np.eye(nu) + np.einsum("ki,ij->kij", rng.uniform(size=(N, nu)), np.eye(nu))
     elif cfg == 4:
-        A = np.stack([0.99 * _haar(rng, nx) for _ in range(N)]) + 0.01 * rng.standard_normal((N, nx, nx))
+        A = 0.99 * _haar(rng, nx, N) + 0.01 * rng.standard_normal((N, nx, nx))
         B = rng.standard_normal((N, nx, nu)) / np.sqrt(nx)
         M = rng.standard_normal((N + 1, nx, nx))
         Q = _sym(M @ np.swapaxes(M, -1, -2)) + eye_x
@@ -166,6 +170,49 @@ def make_batch(cfg: int, batch=None, N=None, nx=None, nu=None, start=0) -> LQPro
     insts = [make_instance(cfg, start + i, N=N or N0, nx=nx or nx0, nu=nu or nu0) for i in range(batch)]
     out = stack(insts)
     out.meta = {"cfg": cfg, "start": start}
+    return out
+
+
+def _instance_worker(args):
+    cfg, i, N, nx, nu = args
+    p = make_instance(cfg, i, N=N, nx=nx, nu=nu)
+    return i, {k: getattr(p, k) for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+
+
+def make_batch_parallel(cfg: int, batch=None, workers=8, N=None, nx=None, nu=None, progress=None) -> LQProblem:
+    """``make_batch`` with the instances drawn in `workers` processes (each instance has its own
+    seed, so the result is identical), written into preallocated batch arrays as they arrive;
+    for the workloads whose instances take seconds to draw.  progress(done, total) is called
+    every few instances."""
+    import multiprocessing as mp
+    b0, N0, nx0, nu0 = config_sizes(cfg)
+    batch = b0 if batch is None else batch
+    N, nx, nu = N or N0, nx or nx0, nu or nu0
+    shapes = {"A": (N, nx, nx), "B": (N, nx, nu), "Q": (N + 1, nx, nx), "R": (N, nu, nu), "q": (N + 1, nx),
+              "r": (N, nu), "x0": (nx,)}
+    arrs = {k: np.empty((batch,) + s_) for k, s_ in shapes.items()}
+    jobs = [(cfg, i, N, nx, nu) for i in range(batch)]
+    done = 0
+    # one BLAS thread per worker process (the workers inherit the environment at their start)
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    os.environ.update({k: "1" for k in keys})
+    try:
+        with mp.get_context("spawn").Pool(max(1, min(workers, batch))) as pool:
+            for i, d in pool.imap_unordered(_instance_worker, jobs):
+                for k, v in d.items():
+                    arrs[k][i] = v
+                done += 1
+                if progress and (done % 8 == 0 or done == batch):
+                    progress(done, batch)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    out = LQProblem(**arrs)
+    out.meta = {"cfg": cfg, "start": 0}
     return out
 
 

@@ -153,15 +153,19 @@ def test_adjoint_workload_full_size_sampled():
 
 
 def test_large_workload_full_size_sampled():
-    """Workload 4's shape and batch (64 instances, N = 1000, nx = 128, nu = 32; four distinct
-    instances repeated to keep generation short): float64 and mixed, residual of every instance,
-    oracle (textbook Riccati) on a sample."""
-    inst = [synth.make_instance(4, i) for i in range(4)]
-    insts = [inst[i % 4] for i in range(64)]
+    """Workload 4 at its full size (64 distinct instances, N = 1000, nx = 128, nu = 32, drawn in
+    up to sixteen processes): float64 and mixed, residual of every instance, oracle (textbook Riccati)
+    on a sample."""
+    import os
+    b = synth.make_batch_parallel(4, workers=min(16, os.cpu_count() or 1),
+                                  progress=lambda d, t: print(f"  drawn {d}/{t} instances", flush=True))
+    assert b.batch == 64 and len({float(b.A[i, 0, 0, 0]) for i in range(64)}) == 64
+    insts = [b.instance(i) for i in range(64)]
     print("case: workload 4 full size, tile", flush=True)
     for mode, mi in (("f64", 0), ("mixed_f32", 8), ("mixed_bf16", 30)):
-        res = run(insts, mode, max_it=mi)
+        res = run(b, mode, max_it=mi, plan=L.Plan(b.N, b.nx, b.nu, batch=64, mode=mode))
         assert res["plan"].variant == "tile"
+        res["insts"] = insts
         _check(res, sample=[0, 1, 63])
 
 

@@ -219,6 +219,29 @@ int lq_solve_backward(const lq_plan* plan, const lq_data* data, void* workspace,
                       double* gf, double* gx0, double* rel_res, int32_t* iters, int32_t* info,
                       hipStream_t stream);
 
+/* Factor + solve of a uniform batch WITHOUT ANY DEVICE ALLOCATION, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same size-specialised kernels as lq_factor + lq_solve on a plan of this batch (identical
+ * results), with the workspace in a library-owned device array of LQ_NOALLOC_SCRATCH_BYTES per GPU
+ * instead of a caller workspace, and no plan.
+ *   batch, N, nx, nu   uniform sizes; (nx, nu) must have a size-specialised kernel
+ *                      ((12,4), (4,2), (8,4), (10,6), (6,2)), else LQ_EUNSUPPORTED
+ *   mode               LQ_F64 or LQ_MIXED_F32
+ *   data               device arrays in the layout above, every one 16-byte aligned (LQ_EINVAL
+ *                      otherwise)
+ *   opts, x, u, lam, rel_res, iters, info   as in lq_solve (info is written, not read)
+ * Limit: batch (N+1) FS f + batch (N nu + (N+1) nx) 8 + batch (2 N nu + 2 (N+1) nx + N nx) 8 bytes,
+ * each term rounded up to 256, must not exceed LQ_NOALLOC_SCRATCH_BYTES (FS = nu(nu+1)/2 + nu +
+ * nx nu + nx(nx+1)/2 + nx, f = 8 in LQ_F64 and 4 in LQ_MIXED_F32); larger batches are refused with
+ * LQ_EUNSUPPORTED before anything is launched.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on a GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero.  Returns as lq_factor / lq_solve. */
+#define LQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lq_factor_solve_noalloc(int32_t batch, int32_t N, int32_t nx, int32_t nu, lq_mode mode,
+                            const lq_data* data, const lq_solve_opts* opts, double* x, double* u,
+                            double* lam, double* rel_res, int32_t* iters, int32_t* info,
+                            hipStream_t stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* lq_last_error(void);
 

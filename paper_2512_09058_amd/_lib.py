@@ -43,6 +43,8 @@ EXPORTS = {
                  + [C.c_void_p] * 6 + [C.c_void_p]),
     "lq_solve_backward": (C.c_int, [C.c_void_p, C.POINTER(LqData), C.c_void_p, C.POINTER(LqSolveOpts)]
                           + [C.c_void_p] * 17 + [C.c_void_p]),
+    "lq_factor_solve_noalloc": (C.c_int, [C.c_int32] * 4 + [C.c_int, C.POINTER(LqData), C.POINTER(LqSolveOpts)]
+                                + [C.c_void_p] * 6 + [C.c_void_p]),
 }
 
 _lib = None

@@ -147,6 +147,19 @@ def solve_backward(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, 
                                 _ptr(info), _stream(stream)), "lq_solve_backward")
 
 
+def factor_solve_noalloc(batch: int, N: int, nx: int, nu: int, data: Dict[str, torch.Tensor], x, u, lam,
+                         rel_res=None, iters=None, info=None, mode: str = "f64", tol: float = 1e-10,
+                         max_it: int = 0, check_res: bool = True, stream=None):
+    """lq_factor_solve_noalloc: factor + solve of a uniform batch with the library's own device
+    scratch array as workspace (no plan, no allocation; see the header for the size limit)."""
+    lib = _lib.load()
+    dd = _data(data)
+    o = LqSolveOpts(float(tol), int(max_it), int(bool(check_res)))
+    check(lib.lq_factor_solve_noalloc(int(batch), int(N), int(nx), int(nu), MODES[mode], C.byref(dd), C.byref(o),
+                                      _ptr(x), _ptr(u), _ptr(lam), _ptr(rel_res), _ptr(iters), _ptr(info),
+                                      _stream(stream)), "lq_factor_solve_noalloc")
+
+
 # ---------------------------------------------------------------------------------------------
 # Packing of problems into the boundary layout (instance blocks back to back, row-major).
 

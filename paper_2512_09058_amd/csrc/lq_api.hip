@@ -671,3 +671,96 @@ extern "C" int lq_solve_backward(const lq_plan* p, const lq_data* d, void* ws, c
   e = lq::launch_grad_generic(g, st);
   return launch_status(e, "lq_solve_backward");
 }
+
+// ---------------------------------------------------------------------------------------------
+// Factor + solve without any allocation, for callers that cannot allocate device memory.  The
+// workspace lives in a file-scope device array (one copy per GPU, held until the process ends);
+// host code reaches it only through the address hipGetSymbolAddress returns for the current
+// device, never through the array's name.
+
+namespace {
+constexpr size_t kNoAllocScratchBytes = LQ_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device ordinal -> device address of `scratch`
+
+// Address of this device's copy of `scratch` (looked up once per device, with it current).
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return LQ_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    return fail(LQ_EHIP, "lq_factor_solve_noalloc: hipGetSymbolAddress of the scratch array failed: %s",
+                hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return LQ_OK;
+}
+}  // namespace
+
+// Scratch bytes a uniform batch needs: factors, sweep vectors, refinement state, each 256-byte aligned.
+static size_t noalloc_required_bytes(int32_t batch, int32_t N, int32_t nx, int32_t nu, lq_mode mode) {
+  const size_t fb = mode == LQ_F64 ? sizeof(double) : sizeof(float);
+  const size_t b = (size_t)batch, n = (size_t)N, x = (size_t)nx, u = (size_t)nu;
+  size_t o = align256(b * (n + 1) * (size_t)lq::stage_factor_elems(nx, nu) * fb);  // factors
+  o = align256(o + b * (n * u + (n + 1) * x) * sizeof(double));                  // sweep vectors
+  o = align256(o + b * (size_t)lq::v2_elems(N, nx, nu) * sizeof(double));        // refinement state
+  return o;
+}
+
+extern "C" int lq_factor_solve_noalloc(int32_t batch, int32_t N, int32_t nx, int32_t nu, lq_mode mode,
+                                       const lq_data* d, const lq_solve_opts* o, double* x, double* u,
+                                       double* lam, double* rel_res, int32_t* iters, int32_t* info,
+                                       hipStream_t st) {
+  g_err.clear();
+  const char* fn = "lq_factor_solve_noalloc";
+  if (batch <= 0 || N <= 0 || nx <= 0 || nu <= 0)
+    return fail(LQ_EINVAL, "%s: batch, N, nx, nu must be positive", fn);
+  if (mode != LQ_F64 && mode != LQ_MIXED_F32) return fail(LQ_EUNSUPPORTED, "%s: mode must be LQ_F64 or LQ_MIXED_F32", fn);
+  if (!lq::small_variant_available(mode, nx, nu))
+    return fail(LQ_EUNSUPPORTED, "%s: no size-specialised kernel for nx=%d nu=%d", fn, nx, nu);
+  if (!d || !d->A || !d->B || !d->Q || !d->R || !d->q || !d->r || !d->x0)
+    return fail(LQ_EINVAL, "%s: A, B, Q, R, q, r, x0 are required", fn);
+  int rc = check_opts(o, fn);
+  if (rc) return rc;
+  if (!x || !u || !lam || !info) return fail(LQ_EINVAL, "%s: x, u, lam, info are required", fn);
+  const size_t need = noalloc_required_bytes(batch, N, nx, nu, mode);
+  if (need > kNoAllocScratchBytes)
+    return fail(LQ_EUNSUPPORTED, "%s: batch %d x N %d (nx %d, nu %d) needs %zu bytes of scratch, above the %zu available",
+                fn, batch, N, nx, nu, need, kNoAllocScratchBytes);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LQ_EHIP, "%s: hipGetDevice failed", fn);
+  void* ws = nullptr;
+  if ((rc = scratch_address(dev, &ws))) return rc;
+  if (!lq::small_aligned(*d, ws)) return fail(LQ_EINVAL, "%s: every data array must be 16-byte aligned", fn);
+  const size_t fb = mode == LQ_F64 ? sizeof(double) : sizeof(float);
+  char* w = (char*)ws;
+  void* F = w;
+  double* V = (double*)(w + align256((size_t)batch * (N + 1) * (size_t)lq::stage_factor_elems(nx, nu) * fb));
+  double* V2 = (double*)((char*)V + align256((size_t)batch * ((size_t)N * nu + (size_t)(N + 1) * nx) * sizeof(double)));
+  hipError_t e = lq::launch_factor_small(mode, batch, N, nx, nu, *d, F, V, info, st);
+  if ((rc = launch_status(e, fn))) return rc;
+  lq::SolveArgs a;
+  memset(&a, 0, sizeof a);
+  a.batch = batch;
+  a.d = *d;
+  a.F = F;
+  a.V = V;
+  a.V2 = V2;
+  a.tol = o->tol;
+  a.max_it = o->max_it;
+  a.check = o->check;
+  a.x = x; a.u = u; a.lam = lam;
+  a.rhs = lq::RHS_PRIMAL;
+  a.rel_res = rel_res; a.iters = iters; a.info = info;
+  e = lq::launch_solve_small(mode, N, nx, nu, a, st);
+  return launch_status(e, fn);
+}

@@ -45,6 +45,13 @@ EXPORTS = {
                           + [C.c_void_p] * 17 + [C.c_void_p]),
     "lq_factor_solve_noalloc": (C.c_int, [C.c_int32] * 4 + [C.c_int, C.POINTER(LqData), C.POINTER(LqSolveOpts)]
                                 + [C.c_void_p] * 6 + [C.c_void_p]),
+    # block-tridiagonal solvers (include/lqblocktri.h)
+    "lq_bt_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int]),
+    "lq_bt_cr_factor": (C.c_int, [C.c_int32] * 3 + [C.c_void_p] * 4 + [C.c_void_p]),
+    "lq_bt_cr_solve": (C.c_int, [C.c_int32] * 3 + [C.c_void_p] * 3 + [C.c_void_p]),
+    "lq_bt_pcr_solve": (C.c_int, [C.c_int32] * 3 + [C.c_void_p] * 6 + [C.c_void_p]),
+    "lq_bt_pcg": (C.c_int, [C.c_int32] * 3 + [C.c_void_p] * 4 + [C.c_int32, C.c_double, C.c_int32]
+                  + [C.c_void_p] * 4 + [C.c_void_p]),
 }
 
 _lib = None

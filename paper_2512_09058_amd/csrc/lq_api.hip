@@ -91,6 +91,19 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+namespace lq {
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+void clear_error() { g_err.clear(); }
+}  // namespace lq
+
 static const size_t kLdsLimit = 160 * 1024;
 
 enum Variant : int32_t { VAR_GENERIC = 0, VAR_SMALL = 1, VAR_TILE = 2 };

@@ -159,4 +159,10 @@ struct GradArgs {
   double *gA, *gB, *gQ, *gR, *gS, *gq, *gr, *gf, *gx0;
 };
 
+// Error message of the calling thread (lq_last_error): set_error records it and returns code.
+int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+// Raise (never lower) a kernel's dynamic-LDS limit.
+hipError_t raise_lds_limit(const void* kernel, size_t lds);
+
 }  // namespace lq

@@ -15,3 +15,4 @@ from .problems import (  # noqa: F401
     random_problem,
     stack,
 )
+from .blocktri import random_blocktri  # noqa: F401

@@ -449,6 +449,19 @@ def factor_flops(batch, N, nx, nu):
     return 2.0 * batch * N * (0.5 * ux * nx * nx + 0.5 * ux * ux * nx + ux ** 3 / 6.0)
 
 
+def pit_factor_flops(batch, N, nx, nu, P):
+    """Operation count of the parallel-in-time factorisation (FMA = 2 flops), summed over every
+    interval (the paper's eq. flop gives the same terms per interval on the critical path): per
+    stage potrf 1/6 nux^3, trsm 1/2 nx nu^2, gemm nx^2 nu, M^fwd syrk 1/2 nu nx^2; per stage but the
+    interval's first trmm 1/2 nux nx^2, syrk 1/2 nux^2 nx and the propagation gemm nux nx^2;
+    per interval 1/2 nx^3 (L^A) + 4/3 nx^3 (Schur blocks); cyclic reduction about 3 nx^3 per block."""
+    ux = nx + nu
+    n = N / P
+    per = (n * (ux ** 3 / 6 + 0.5 * nx * nu * nu + nx * nx * nu + 0.5 * nu * nx * nx)
+           + (n - 1) * (1.5 * ux * nx * nx + 0.5 * ux * ux * nx) + 0.5 * nx ** 3 + 4.0 / 3.0 * nx ** 3 + 3 * nx ** 3)
+    return 2.0 * batch * P * per
+
+
 def bench_large(args):
     """The large workload: 64 instances, N = 1000, nx = 128, nu = 32 (A = 0.99 Haar + 0.01 G,
     B = G / sqrt(nx), Q = M M^T + I, R = I); bf16 matrix-core stage products with float64
@@ -496,6 +509,42 @@ def bench_large(args):
         res[mode] = r
         print(f"[bench] large {mode}: factor {tf:.1f} ms, solve {tsv:.1f} ms, max rel_res {relh.max():.2e}, "
               f"iterations {r['iters_max']}", file=sys.stderr, flush=True)
+    # the parallel-in-time path (FP64): each instance's horizon in P intervals factored at once
+    from paper_2512_09058_amd import pit
+    for P in args.pit_intervals:
+        plan = pit.PitPlan(b, Nn, nx, nu, P)
+        ws = plan.workspace()
+        info = torch.zeros(b, dtype=torch.int32, device="cuda")
+        rel = torch.zeros(b, dtype=torch.float64, device="cuda")
+        x, u, lam = plan.empty_outputs()
+        stream = torch.cuda.current_stream()
+        ev = []
+        for s_ in range(args.warmup + args.steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            pit.factor(plan, data, ws, info, stream=stream)
+            e[1].record(stream)
+            pit.solve(plan, data, ws, x, u, lam, rel, info, stream=stream)
+            e[2].record(stream)
+            if s_ >= args.warmup:
+                ev.append(e)
+        torch.cuda.synchronize()
+        tf = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        tsv = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        relh = rel.cpu().numpy()
+        sol = [t_.view(b, Nn, -1)[0].cpu().numpy() for t_ in (x, u, lam)]
+        fl = pit_factor_flops(b, Nn, nx, nu, P)
+        res[f"pit_P{P}"] = {"value": b / ((tf + tsv) * 1e-3), "ms_per_step": tf + tsv, "ms_factor": tf, "ms_solve": tsv,
+                            "max_rel_res": float(relh.max()), "info_ok": bool((info == 0).all().item()),
+                            "workgroups_factor": b * P, "fwd_err_vs_serial_f64_inst0": _fwd_err(sol, sols0["f64"]),
+                            "factor_roofline": {"bound": "alu", "achieved": fl / (tf * 1e-3) / 1e12,
+                                                "peak": 78.6, "unit": "TFLOP/s",
+                                                "frac": fl / (tf * 1e-3) / 1e12 / 78.6,
+                                                "algorithmic_flops_per_launch": fl, "ms_per_launch": tf}}
+        sols0[f"pit_P{P}"] = sol
+        print(f"[bench] large pit P={P}: factor {tf:.1f} ms, solve {tsv:.1f} ms, max rel_res {relh.max():.2e}",
+              file=sys.stderr, flush=True)
+        del ws
     m = res["mixed_bf16"]
     dom_solve = m["ms_solve"] >= m["ms_factor"]
     out = {"metric": "LQ KKT solves/s, batch 64 nx=128 nu=32 N=1000: bf16 products + f64 refinement vs FP64",
@@ -669,6 +718,81 @@ def bench_single(args):
     print(json.dumps(out))
 
 
+def bench_blocktri(args):
+    """Batched block-tridiagonal systems (64 systems of 64 blocks of 128: the Schur complement
+    shape of a 64-interval split of the large workload): cyclic-reduction factorisation and solve,
+    parallel cyclic reduction, PCG with the stair preconditioner; the oracle's written-out CR
+    recursion and dense solve timed on the host."""
+    import torch
+    import synth
+    from paper_2512_09058_amd import blocktri as btl
+    from oracle import blocktri as obt
+    batch, Nb, n = 64, 64, 128
+    M, K, b = synth.random_blocktri(1, batch, Nb, n)
+    Md, Kd, bd = (torch.from_numpy(a).to("cuda") for a in (M, K, b))
+    ws = btl.workspace(batch, Nb, n, "cr")
+    info = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    x = torch.empty_like(bd)
+    stream = torch.cuda.current_stream()
+    t = {"cr_factor": [], "cr_solve": [], "pcr": [], "pcg_stair": []}
+    wsp = btl.workspace(batch, Nb, n, "pcr")
+    wsg = btl.workspace(batch, Nb, n, "pcg")
+    xp = torch.empty_like(bd)
+    xg = torch.empty_like(bd)
+    its = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    relg = torch.zeros(batch, dtype=torch.float64, device="cuda")
+    infog = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    for s_ in range(args.warmup + args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record(stream)
+        btl.cr_factor(Md, Kd, ws, info, stream=stream)
+        e[1].record(stream)
+        btl.cr_solve(batch, Nb, n, ws, bd, x, stream=stream)
+        e[2].record(stream)
+        btl.pcr_solve(Md, Kd, bd, xp, wsp, info, stream=stream)
+        e[3].record(stream)
+        btl.pcg(Md, Kd, bd, "stair", 1e-12, 200, xg, wsg, its, relg, infog, stream=stream)
+        e[4].record(stream)
+        if s_ >= args.warmup:
+            for i, k in enumerate(t):
+                t[k].append(e)
+    torch.cuda.synchronize()
+    ms = {k: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in v])) for i, (k, v) in enumerate(t.items())}
+    xh, xph, xgh = x.cpu().numpy(), xp.cpu().numpy(), xg.cpu().numpy()
+    errs = {}
+    for sidx in (0, 63):
+        ref = obt.cr_recursive(M[sidx], K[sidx], b[sidx])
+        for name, arr in (("cr", xh), ("pcr", xph), ("pcg", xgh)):
+            errs[name] = max(errs.get(name, 0.0), float(np.abs(arr[sidx] - ref).max() / np.abs(ref).max()))
+    fl = 2.0 * batch * Nb * (7.0 / 6.0 + 2.0) * n ** 3  # eliminations + updates of the remaining rows
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        cnt = 0
+        while time.perf_counter() - t0 < 10.0 and cnt < batch:
+            obt.cr_recursive(M[cnt], K[cnt], b[cnt])
+            cnt += 1
+        tc = (time.perf_counter() - t0) / cnt
+        cpu = {"value": 1.0 / tc, "unit": "systems/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{cnt} systems through the oracle's written-out cyclic-reduction recursion (numpy float64, "
+                         f"one process; numpy's BLAS threads as loaded), {tc * 1e3:.0f} ms per system"}
+    out = {"metric": "batched block-tridiagonal solves/s, 64 systems x 64 blocks of 128 (CR factor + solve)",
+           "value": batch / ((ms["cr_factor"] + ms["cr_solve"]) * 1e-3), "unit": "systems/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms["cr_factor"] + ms["cr_solve"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded SPD block-tridiagonal systems)",
+           "config": {"workload": "64 systems, Nb=64 blocks of n=128", "batch": batch, "Nb": Nb, "n": n},
+           "ms": ms, "pcg_iters_max": int(its.max().item()), "rel_err_vs_oracle_sampled": errs,
+           "info_ok": bool((info == 0).all().item()),
+           "roofline": {"bound": "alu", "kernel": "cr_factor (k_cr_elim + k_cr_update)",
+                        "achieved": fl / (ms["cr_factor"] * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": fl / (ms["cr_factor"] * 1e-3) / 1e12 / 78.6, "traffic": None,
+                        "algorithmic_flops_per_launch": fl, "ms_per_launch": ms["cr_factor"]},
+           "cpu_baseline": cpu}
+    print(f"[bench] blocktri: {ms}", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -680,7 +804,9 @@ def main():
     ap.add_argument("--distinct", type=int, default=0,
                     help="large / adjoint workloads: generate only this many distinct instances and repeat them "
                          "(0: all distinct)")
-    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20"],
+    ap.add_argument("--pit-intervals", type=int, nargs="*", default=[4, 8, 16],
+                    help="large workload: interval counts of the parallel-in-time path")
+    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20", "blocktri"],
                     default="batch4096",
                     help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
                          "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")
@@ -718,6 +844,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "single20":
         return bench_single(args)
+    if args.workload == "blocktri":
+        return bench_blocktri(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)

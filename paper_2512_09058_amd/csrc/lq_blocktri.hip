@@ -37,7 +37,7 @@ struct BT {
 __host__ __device__ inline int64_t blk(const BT& t, int b, int k) { return ((int64_t)b * t.Nb + k) * t.nn; }
 
 // Copy M into the working diagonal blocks and K into the coupling slots: Kw[k] = C(k, k - 1) = K_{k-1}.
-__global__ void __launch_bounds__(NT) k_cr_init(BT t, const double* __restrict__ M, const double* __restrict__ K,
+__global__ void __launch_bounds__(NT, 2) k_cr_init(BT t, const double* __restrict__ M, const double* __restrict__ K,
                                                 double* Lw, double* Kw) {
   const int k = blockIdx.x, b = blockIdx.y;
   const double* src = M + blk(t, b, k);
@@ -55,7 +55,7 @@ __device__ inline void report(int32_t* info, int b, int code) {
 }
 
 // Level l eliminations: block k = s (2 i + 1) for i = blockIdx.x.
-__global__ void __launch_bounds__(NT) k_cr_elim(BT t, int s, double* Lw, const double* Kw, double* U, double* Y,
+__global__ void __launch_bounds__(NT, 2) k_cr_elim(BT t, int s, double* Lw, const double* Kw, double* U, double* Y,
                                                 int32_t* info) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(NT) k_cr_elim(BT t, int s, double* Lw, const d
 }
 
 // Level l updates of the rows that remain: j = 2 s i for i = blockIdx.x.
-__global__ void __launch_bounds__(NT) k_cr_update(BT t, int s, double* Lw, double* Kw, const double* U, const double* Y) {
+__global__ void __launch_bounds__(NT, 2) k_cr_update(BT t, int s, double* Lw, double* Kw, const double* U, const double* Y) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
   const int j = 2 * s * blockIdx.x, b = blockIdx.y, n = t.n;
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(NT) k_cr_update(BT t, int s, double* Lw, doubl
     wg::gemm<false, true, 0>(n, n, n, -1.0, Y + blk(t, b, j - s), n, U + blk(t, b, j - s), n, 0.0, Kw + blk(t, b, j), n, sm);
 }
 
-__global__ void __launch_bounds__(NT) k_cr_last(BT t, double* Lw, int32_t* info) {
+__global__ void __launch_bounds__(NT, 2) k_cr_last(BT t, double* Lw, int32_t* info) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
   const int b = blockIdx.x;
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(NT) k_cr_last(BT t, double* Lw, int32_t* info)
 
 // Solution with the CR factors, one workgroup per system: forward substitution level by level,
 // then recovery of the eliminated unknowns (eq. cr-odd) from the last level back.
-__global__ void __launch_bounds__(NT) k_cr_solve(BT t, const double* Lw, const double* U, const double* Y,
+__global__ void __launch_bounds__(NT, 2) k_cr_solve(BT t, const double* Lw, const double* U, const double* Y,
                                                  const double* __restrict__ rhs, double* x) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
@@ -108,8 +108,8 @@ __global__ void __launch_bounds__(NT) k_cr_solve(BT t, const double* Lw, const d
     const int s = 1 << l;
     for (int k = s; k < Nb; k += 2 * s) wg::trsv<false>(n, Lw + blk(t, b, k), n, xb + (int64_t)k * n, sm);
     for (int j = 0; j < Nb; j += 2 * s) {  // b_j -= Y_{j-s} bt_{j-s} + U_{j+s} bt_{j+s}
-      if (j >= s) wg::gemv<false>(n, n, -1.0, Y + blk(t, b, j - s), n, xb + (int64_t)(j - s) * n, 1.0, xb + (int64_t)j * n);
-      if (j + s < Nb) wg::gemv<false>(n, n, -1.0, U + blk(t, b, j + s), n, xb + (int64_t)(j + s) * n, 1.0, xb + (int64_t)j * n);
+      if (j >= s) wg::gemv<false>(n, n, -1.0, Y + blk(t, b, j - s), n, xb + (int64_t)(j - s) * n, 1.0, xb + (int64_t)j * n, sm);
+      if (j + s < Nb) wg::gemv<false>(n, n, -1.0, U + blk(t, b, j + s), n, xb + (int64_t)(j + s) * n, 1.0, xb + (int64_t)j * n, sm);
     }
   }
   wg::trsv<false>(n, Lw + blk(t, b, 0), n, xb, sm);
@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(NT) k_cr_solve(BT t, const double* Lw, const d
     const int s = 1 << l;
     for (int k = s; k < Nb; k += 2 * s) {  // x_k = L^{-T} (bt_k - U_k^T x_{k-s} - Y_k^T x_{k+s})
       double* xk = xb + (int64_t)k * n;
-      wg::gemv<true>(n, n, -1.0, U + blk(t, b, k), n, xb + (int64_t)(k - s) * n, 1.0, xk);
-      if (k + s < Nb) wg::gemv<true>(n, n, -1.0, Y + blk(t, b, k), n, xb + (int64_t)(k + s) * n, 1.0, xk);
+      wg::gemv<true>(n, n, -1.0, U + blk(t, b, k), n, xb + (int64_t)(k - s) * n, 1.0, xk, sm);
+      if (k + s < Nb) wg::gemv<true>(n, n, -1.0, Y + blk(t, b, k), n, xb + (int64_t)(k + s) * n, 1.0, xk, sm);
       wg::trsv<true>(n, Lw + blk(t, b, k), n, xk, sm);
     }
   }
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(NT) k_cr_solve(BT t, const double* Lw, const d
 // Working arrays: Mw, Kw (Kw[k] = C(k + s, k), the coupling to the row s below), bw; per level
 // the factors L, Y, U and bt = L^{-1} b, then the next level's M2, K2, b2.
 
-__global__ void __launch_bounds__(NT) k_pcr_init(BT t, const double* __restrict__ M, const double* __restrict__ K,
+__global__ void __launch_bounds__(NT, 2) k_pcr_init(BT t, const double* __restrict__ M, const double* __restrict__ K,
                                                  const double* __restrict__ rhs, double* Mw, double* Kw, double* bw) {
   const int k = blockIdx.x, b = blockIdx.y, n = t.n;
   for (int64_t e = threadIdx.x; e < t.nn; e += NT) Mw[blk(t, b, k) + e] = M[blk(t, b, k) + e];
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(NT) k_pcr_init(BT t, const double* __restrict_
   for (int e = threadIdx.x; e < n; e += NT) bw[vo + e] = rhs[vo + e];
 }
 
-__global__ void __launch_bounds__(NT) k_pcr_elim(BT t, int s, const double* Mw, const double* Kw, const double* bw,
+__global__ void __launch_bounds__(NT, 2) k_pcr_elim(BT t, int s, const double* Mw, const double* Kw, const double* bw,
                                                  double* L, double* U, double* Y, double* bt, int32_t* info) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(NT) k_pcr_elim(BT t, int s, const double* Mw, 
   wg::trsv<false>(n, Lk, n, bt + vo, sm);
 }
 
-__global__ void __launch_bounds__(NT) k_pcr_update(BT t, int s, const double* Mw, const double* bw, const double* U,
+__global__ void __launch_bounds__(NT, 2) k_pcr_update(BT t, int s, const double* Mw, const double* bw, const double* U,
                                                    const double* Y, const double* bt, double* M2, double* K2,
                                                    double* b2) {
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -177,11 +177,11 @@ __global__ void __launch_bounds__(NT) k_pcr_update(BT t, int s, const double* Mw
   wg::copy(1, n, bw + vo, n, b2 + vo, n);
   if (k - s >= 0) {
     wg::gemm<false, true, 1>(n, n, n, -1.0, Y + blk(t, b, k - s), n, Y + blk(t, b, k - s), n, 1.0, Mk, n, sm);
-    wg::gemv<false>(n, n, -1.0, Y + blk(t, b, k - s), n, bt + vo - (int64_t)s * n, 1.0, b2 + vo);
+    wg::gemv<false>(n, n, -1.0, Y + blk(t, b, k - s), n, bt + vo - (int64_t)s * n, 1.0, b2 + vo, sm);
   }
   if (k + s < t.Nb) {
     wg::gemm<false, true, 1>(n, n, n, -1.0, U + blk(t, b, k + s), n, U + blk(t, b, k + s), n, 1.0, Mk, n, sm);
-    wg::gemv<false>(n, n, -1.0, U + blk(t, b, k + s), n, bt + vo + (int64_t)s * n, 1.0, b2 + vo);
+    wg::gemv<false>(n, n, -1.0, U + blk(t, b, k + s), n, bt + vo + (int64_t)s * n, 1.0, b2 + vo, sm);
   }
   if (k + 2 * s < t.Nb)  // C(k + 2s, k) = -Y_{k+s} U_{k+s}^T
     wg::gemm<false, true, 0>(n, n, n, -1.0, Y + blk(t, b, k + s), n, U + blk(t, b, k + s), n, 0.0, K2 + blk(t, b, k), n, sm);
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(NT) k_pcr_update(BT t, int s, const double* Mw
     wg::fill(n, n, 0.0, K2 + blk(t, b, k), n);
 }
 
-__global__ void __launch_bounds__(NT) k_pcr_last(BT t, const double* Mw, const double* bw, double* L, double* x,
+__global__ void __launch_bounds__(NT, 2) k_pcr_last(BT t, const double* Mw, const double* bw, double* L, double* x,
                                                  int32_t* info) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_pcr_last(BT t, const double* Mw, const d
 // Block-Jacobi (D^{-1}) and stair (D^{-1} (I - Koff D^{-1})) preconditioners from the explicit
 // inverses D_k^{-1} = L_k^{-T} L_k^{-1} of the diagonal blocks, formed once.
 
-__global__ void __launch_bounds__(NT) k_pcg_inv(BT t, const double* __restrict__ M, double* L, double* Dinv,
+__global__ void __launch_bounds__(NT, 2) k_pcg_inv(BT t, const double* __restrict__ M, double* L, double* Dinv,
                                                 int32_t* info) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
@@ -281,7 +281,7 @@ __device__ inline void bt_koff(const BT& t, int b, const double* K, const double
   wg::sync();
 }
 
-__global__ void __launch_bounds__(NT) k_pcg(BT t, const double* __restrict__ M, const double* __restrict__ K,
+__global__ void __launch_bounds__(NT, 2) k_pcg(BT t, const double* __restrict__ M, const double* __restrict__ K,
                                             const double* __restrict__ rhs, const double* Dinv, int stair, double tol,
                                             int max_it, double* x, double* work, int32_t* iters, double* relres,
                                             int32_t* info) {

@@ -89,38 +89,49 @@ __device__ inline double* fblk(const PG& g, double* ws, int b, int j) { return w
 // x <- L^{-1} x (TR = false) or L^{-T} x (TR = true), n <= NT; x in global memory.
 template <bool TR>
 __device__ void pk_trsv(int n, const double* Lp, const double* dinv, double* x, wg::Smem& sm) {
-  const int i = threadIdx.x;
-  wg::sync();
-  if (i < n) sm.red[i] = x[i];
-  for (int s = 0; s < n; ++s) {
-    const int t = TR ? n - 1 - s : s;
-    wg::sync();
-    const double xt = sm.red[t] * dinv[t];
-    wg::sync();
-    if (i == t) sm.red[i] = xt;
-    else if (!TR && i > t && i < n) sm.red[i] = fma(-Lp[(int64_t)i * (i + 1) / 2 + t], xt, sm.red[i]);
-    else if (TR && i < t) sm.red[i] = fma(-Lp[(int64_t)t * (t + 1) / 2 + i], xt, sm.red[i]);
-  }
-  wg::sync();
-  if (i < n) x[i] = sm.red[i];
-  wg::sync();
+  wg::trsv_blocked<TR>(
+      n, [&](int i, int j) { return Lp[(int64_t)i * (i + 1) / 2 + j]; }, [&](int i) { return dinv[i]; }, x, sm);
 }
 
-// y = L x (TR = false) or y = L^T x (TR = true) (+ y when ACC); x and y must not overlap.
+// y = L x (TR = false) or y = L^T x (TR = true) (+ y when ACC); x and y must not overlap.  Both
+// read the packed rows coalesced: L x with a wavefront per row; L^T x with the rows dealt over the
+// wavefronts (lanes over the columns) and the partial sums added through LDS.
 template <bool TR, bool ACC>
-__device__ void pk_trmv(int n, const double* Lp, const double* x, double* y) {
+__device__ void pk_trmv(int n, const double* Lp, const double* x, double* y, wg::Smem& sm) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   wg::sync();
-  for (int i = threadIdx.x; i < n; i += NT) {
-    double s = ACC ? y[i] : 0.0;
-    if (!TR) {
+  if (!TR) {
+    for (int i = w; i < n; i += NW) {
       const double* row = Lp + (int64_t)i * (i + 1) / 2;
-      for (int t = 0; t <= i; ++t) s = fma(row[t], x[t], s);
-    } else {
-      for (int t = i; t < n; ++t) s = fma(Lp[(int64_t)t * (t + 1) / 2 + i], x[t], s);
+      double s = 0.0;
+      for (int t = lane; t <= i; t += 64) s = fma(row[t], x[t], s);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      if (lane == 0) y[i] = ACC ? y[i] + s : s;
     }
-    y[i] = s;
+    wg::sync();
+  } else {
+    double* part = &sm.d[0][0];
+    for (int i0 = 0; i0 < n; i0 += 64) {
+      const int i = i0 + lane;
+      double s = 0.0;
+      if (i < n) {
+#pragma unroll 4
+        for (int t = i0 + ((w - i0) % NW + NW) % NW; t < n; t += NW)  // rows t >= i0, t = w mod NW
+          if (t >= i) s = fma(Lp[(int64_t)t * (t + 1) / 2 + i], x[t], s);
+        part[w * n + i] = s;
+      }
+    }
+    wg::sync();
+    for (int i = threadIdx.x; i < n; i += NT) {
+      double s = ACC ? y[i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s += part[q * n + i];
+      y[i] = s;
+    }
+    wg::sync();
   }
-  wg::sync();
 }
 
 __device__ inline void vcopy(int n, const double* x, double* y) {
@@ -135,7 +146,7 @@ __device__ inline void report(int32_t* info, int b, int code) {
 
 // ---- factorisation ------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(NT) k_pit_factor(PG g, double* ws, int32_t* info) {
+__global__ void __launch_bounds__(NT, 2) k_pit_factor(PG g, double* ws, int32_t* info) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
   const int p = blockIdx.x, b = blockIdx.y;
@@ -211,8 +222,8 @@ __global__ void __launch_bounds__(NT) k_pit_factor(PG g, double* ws, int32_t* in
       // previous stage: W = (L^Q_j)^T [B_{j-1} A_{j-1}],  (B^, A^) = A^cl [B_{j-1} A_{j-1}]
       const double* Bp = mB(g, b, j - 1);
       const double* Ap = mA(g, b, j - 1);
-      wg::gemm<true, false, 0>(nx, nu, nx, 1.0, LQ, nx, Bp, nu, 0.0, W, nux, sm);
-      wg::gemm<true, false, 0>(nx, nx, nx, 1.0, LQ, nx, Ap, nx, 0.0, W + nu, nux, sm);
+      wg::gemm<true, false, 0, true>(nx, nu, nx, 1.0, LQ, nx, Bp, nu, 0.0, W, nux, sm);  // (L^Q)^T upper
+      wg::gemm<true, false, 0, true>(nx, nx, nx, 1.0, LQ, nx, Ap, nx, 0.0, W + nu, nux, sm);
       wg::gemm<false, false, 0>(nx, nu, nx, 1.0, Acl, nx, Bp, nu, 0.0, Ch, nux, sm);
       wg::gemm<false, false, 0>(nx, nx, nx, 1.0, Acl, nx, Ap, nx, 0.0, Ch + nu, nux, sm);
     } else {
@@ -227,7 +238,7 @@ __global__ void __launch_bounds__(NT) k_pit_factor(PG g, double* ws, int32_t* in
 
 // Schur complement blocks of boundary p: D_p = (L^Q_{s_p})^{-T} (L^Q_{s_p})^{-1} + M^fwd_{p-1 mod P}
 // (lower part), K_p = -L^A_(p) (L^Q_{s_p})^{-1} (p <= P - 2).
-__global__ void __launch_bounds__(NT) k_pit_schur(PG g, double* ws) {
+__global__ void __launch_bounds__(NT, 2) k_pit_schur(PG g, double* ws) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
   const int p = blockIdx.x, b = blockIdx.y, nx = g.nx, P = g.P;
@@ -281,7 +292,7 @@ __device__ void stage_rhs(const PG& g, int b, int j, double* rh, double* qh) {
 // with (rhat, qhat) = (r, q) + [B A]^T w, w = L^Q_{j+1} (L^Q_{j+1})^T f_j + p_{j+1} inside the
 // interval, and at its last stage the outgoing coupling times the boundary multiplier (USE_MU).
 template <bool USE_MU>
-__global__ void __launch_bounds__(NT) k_pit_bwd(PG g, double* ws) {
+__global__ void __launch_bounds__(NT, 2) k_pit_bwd(PG g, double* ws) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
   const int p = blockIdx.x, b = blockIdx.y, nx = g.nx, nu = g.nu, N = g.N;
@@ -297,22 +308,22 @@ __global__ void __launch_bounds__(NT) k_pit_bwd(PG g, double* ws) {
       const double* Fn = fblk(g, ws, b, j + 1);
       const double* pn = ws + g.oPv + ((int64_t)b * N + j) * nx;  // p_{j+1}
       if (g.f) {
-        pk_trmv<true, false>(nx, Fn + off_LQ(nx, nu), vf(g, b, j), t);
+        pk_trmv<true, false>(nx, Fn + off_LQ(nx, nu), vf(g, b, j), t, sm);
         vcopy(nx, pn, w);
-        pk_trmv<false, true>(nx, Fn + off_LQ(nx, nu), t, w);
+        pk_trmv<false, true>(nx, Fn + off_LQ(nx, nu), t, w, sm);
       } else {
         vcopy(nx, pn, w);
       }
-      wg::gemv<true>(nx, nu, 1.0, mB(g, b, j), nu, w, 1.0, rh);
-      wg::gemv<true>(nx, nx, 1.0, mA(g, b, j), nx, w, 1.0, qh);
+      wg::gemv<true>(nx, nu, 1.0, mB(g, b, j), nu, w, 1.0, rh, sm);
+      wg::gemv<true>(nx, nx, 1.0, mA(g, b, j), nx, w, 1.0, qh, sm);
     } else if (USE_MU) {
       const double* mu = ws + g.oMu + ((int64_t)b * g.P + (p + 1) % g.P) * nx;
-      wg::gemv<true>(nx, nu, 1.0, mB(g, b, j < N ? j : 0), nu, mu, 1.0, rh);
-      if (j < N) wg::gemv<true>(nx, nx, 1.0, mA(g, b, j), nx, mu, 1.0, qh);
+      wg::gemv<true>(nx, nu, 1.0, mB(g, b, j < N ? j : 0), nu, mu, 1.0, rh, sm);
+      if (j < N) wg::gemv<true>(nx, nx, 1.0, mA(g, b, j), nx, mu, 1.0, qh, sm);
     }
     const double* F = fblk(g, ws, b, j);
     pk_trsv<false>(nu, F, F + off_dR(nx, nu), rh, sm);
-    wg::gemv<false>(nx, nu, -1.0, F + off_LS(nx, nu), nu, rh, 1.0, qh);
+    wg::gemv<false>(nx, nu, -1.0, F + off_LS(nx, nu), nu, rh, 1.0, qh, sm);
     vcopy(nu, rh, ws + g.oRb + ((int64_t)b * N + (j - 1)) * nu);
     vcopy(nx, qh, ws + g.oPv + ((int64_t)b * N + (j - 1)) * nx);
   }
@@ -324,7 +335,7 @@ __global__ void __launch_bounds__(NT) k_pit_bwd(PG g, double* ws) {
 // SOLVE = false (zero multipliers): the interval's part of the Schur right-hand side, the value
 // of its outgoing coupling (B^ u + A^ x at the last stage) and -x_s.  SOLVE = true: x, u, lam.
 template <bool SOLVE>
-__global__ void __launch_bounds__(NT) k_pit_fwd(PG g, double* ws, double* X, double* U, double* LAM) {
+__global__ void __launch_bounds__(NT, 2) k_pit_fwd(PG g, double* ws, double* X, double* U, double* LAM) {
   extern __shared__ __align__(16) unsigned char smraw[];
   wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
   const int p = blockIdx.x, b = blockIdx.y, nx = g.nx, nu = g.nu, N = g.N;
@@ -358,7 +369,7 @@ __global__ void __launch_bounds__(NT) k_pit_fwd(PG g, double* ws, double* X, dou
     const bool wrap = j == N;
     const double* F = fblk(g, ws, b, j);
     const double* rb = ws + g.oRb + ((int64_t)b * N + (j - 1)) * nu;
-    wg::gemv<true>(nx, nu, 1.0, F + off_LS(nx, nu), nu, xv, 0.0, uv);
+    wg::gemv<true>(nx, nu, 1.0, F + off_LS(nx, nu), nu, xv, 0.0, uv, sm);
     wg::sync();
     for (int i = threadIdx.x; i < nu; i += NT) uv[i] = -(uv[i] + rb[i]);
     wg::sync();
@@ -369,8 +380,8 @@ __global__ void __launch_bounds__(NT) k_pit_fwd(PG g, double* ws, double* X, dou
       for (int i = threadIdx.x; i < nx; i += NT) X[((int64_t)b * N + (j - 1)) * nx + i] = xv[i];
     }
     if (j < e) {
-      wg::gemv<false>(nx, nx, 1.0, mA(g, b, j), nx, xv, 0.0, xn);
-      wg::gemv<false>(nx, nu, 1.0, mB(g, b, j), nu, uv, 1.0, xn);
+      wg::gemv<false>(nx, nx, 1.0, mA(g, b, j), nx, xv, 0.0, xn, sm);
+      wg::gemv<false>(nx, nu, 1.0, mB(g, b, j), nu, uv, 1.0, xn, sm);
       if (g.f) {
         wg::sync();
         for (int i = threadIdx.x; i < nx; i += NT) xn[i] += vf(g, b, j)[i];
@@ -378,23 +389,23 @@ __global__ void __launch_bounds__(NT) k_pit_fwd(PG g, double* ws, double* X, dou
       if (SOLVE) {
         const double* Fn = fblk(g, ws, b, j + 1);
         const double* pn = ws + g.oPv + ((int64_t)b * N + j) * nx;
-        pk_trmv<true, false>(nx, Fn + off_LQ(nx, nu), xn, t);
+        pk_trmv<true, false>(nx, Fn + off_LQ(nx, nu), xn, t, sm);
         double* lam = LAM + ((int64_t)b * N + j) * nx;
         vcopy(nx, pn, lam);
-        pk_trmv<false, true>(nx, Fn + off_LQ(nx, nu), t, lam);
+        pk_trmv<false, true>(nx, Fn + off_LQ(nx, nu), t, lam, sm);
       }
       vcopy(nx, xn, xv);
     } else if (!SOLVE) {
       // value of the outgoing coupling at the interval's end: B^ u + A^ x
-      wg::gemv<false>(nx, nu, 1.0, mB(g, b, wrap ? 0 : j), nu, uv, 0.0, gf);
-      if (!wrap) wg::gemv<false>(nx, nx, 1.0, mA(g, b, j), nx, xv, 1.0, gf);
+      wg::gemv<false>(nx, nu, 1.0, mB(g, b, wrap ? 0 : j), nu, uv, 0.0, gf, sm);
+      if (!wrap) wg::gemv<false>(nx, nx, 1.0, mA(g, b, j), nx, xv, 1.0, gf, sm);
     }
   }
 }
 
 // Schur right-hand side of boundary p: g^fwd_{p-1 mod P} + g^bwd_p + f of the boundary's
 // constraint (f_{s_p - 1}, or f_0 + A_0 x_init for p = 0).
-__global__ void __launch_bounds__(NT) k_pit_rhs(PG g, double* ws) {
+__global__ void __launch_bounds__(NT, 2) k_pit_rhs(PG g, double* ws) {
   const int b = blockIdx.x, nx = g.nx, P = g.P;
   const double* x0 = vx0(g, b);
   for (int el = threadIdx.x; el < P * nx; el += NT) {
@@ -418,7 +429,7 @@ __global__ void __launch_bounds__(NT) k_pit_rhs(PG g, double* ws) {
 //   rho_l,k = -f_k - (A_k x_k + B_k u_k - x_{k+1})
 // and the right-hand side entries (-(r_0 + S_0 x_init), -(f_0 + A_0 x_init) for k = 0).
 constexpr int RCH = 8;
-__global__ void __launch_bounds__(NT) k_pit_resid(PG g, const double* X, const double* U, const double* LAM,
+__global__ void __launch_bounds__(NT, 2) k_pit_resid(PG g, const double* X, const double* U, const double* LAM,
                                                   double* ws) {
   const int c = blockIdx.x, b = blockIdx.y, nx = g.nx, nu = g.nu, N = g.N;
   double mr = 0.0, mb = 0.0;

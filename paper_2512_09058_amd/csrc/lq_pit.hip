@@ -427,10 +427,14 @@ __global__ void __launch_bounds__(NT, 2) k_pit_rhs(PG g, double* ws) {
 //   rho_u,k = -r_k - (sym(R_k) u_k + S_k x_k + B_k^T lam_k)            (x_0 = x_init)
 //   rho_x,k = -q_k - (S_k^T u_k + sym(Q_k) x_k + A_k^T lam_k - lam_{k-1}) (k < N; k = N: Q_N x_N - lam_{N-1})
 //   rho_l,k = -f_k - (A_k x_k + B_k u_k - x_{k+1})
-// and the right-hand side entries (-(r_0 + S_0 x_init), -(f_0 + A_0 x_init) for k = 0).
+// and the right-hand side entries (-(r_0 + S_0 x_init), -(f_0 + A_0 x_init) for k = 0).  The
+// products use the coalesced workgroup matrix-vector routines; the vectors stay in LDS.
 constexpr int RCH = 8;
 __global__ void __launch_bounds__(NT, 2) k_pit_resid(PG g, const double* X, const double* U, const double* LAM,
-                                                  double* ws) {
+                                                     double* ws) {
+  extern __shared__ __align__(16) unsigned char smraw[];
+  wg::Smem& sm = *reinterpret_cast<wg::Smem*>(smraw);
+  __shared__ double tv[3][256];
   const int c = blockIdx.x, b = blockIdx.y, nx = g.nx, nu = g.nu, N = g.N;
   double mr = 0.0, mb = 0.0;
   auto up = [&](double rho, double bv) {
@@ -441,80 +445,75 @@ __global__ void __launch_bounds__(NT, 2) k_pit_resid(PG g, const double* X, cons
   const double* x0 = vx0(g, b);
   for (int k = c * RCH; k < (c + 1) * RCH && k <= N; ++k) {
     const double* xk = k == 0 ? x0 : X + ((int64_t)b * N + (k - 1)) * nx;
-    // stationarity in u_k and dynamics rows (k < N)
     if (k < N) {
       const double* uk = U + ((int64_t)b * N + k) * nu;
       const double* lk = LAM + ((int64_t)b * N + k) * nx;
       const double* Rk = mR(g, b, k);
       const double* Bk = mB(g, b, k);
+      // tv0 = sym(R) u + B^T lam, tv1 = S x
+      wg::gemv<false>(nu, nu, 0.5, Rk, nu, uk, 0.0, tv[0], sm);
+      wg::gemv<true>(nu, nu, 0.5, Rk, nu, uk, 1.0, tv[0], sm);
+      wg::gemv<true>(nx, nu, 1.0, Bk, nu, lk, 1.0, tv[0], sm);
+      if (g.S) wg::gemv<false>(nu, nx, 1.0, mS(g, b, k), nx, xk, 0.0, tv[1], sm);
       for (int i = threadIdx.x; i < nu; i += NT) {
-        double a = 0.0;
-        for (int j = 0; j < nu; ++j) a = fma(0.5 * (Rk[i * nu + j] + Rk[j * nu + i]), uk[j], a);
-        double sx = 0.0;
-        if (g.S) {
-          const double* Sr = mS(g, b, k) + (int64_t)i * nx;
-          for (int j = 0; j < nx; ++j) sx = fma(Sr[j], xk[j], sx);
-        }
-        for (int j = 0; j < nx; ++j) a = fma(Bk[(int64_t)j * nu + i], lk[j], a);
-        const double rk = vr(g, b, k)[i];
-        if (k == 0) up(-(rk + sx) - a, rk + sx);
-        else up(-rk - (a + sx), rk);
+        const double rk = vr(g, b, k)[i], sx = g.S ? tv[1][i] : 0.0;
+        up(-rk - (tv[0][i] + sx), k == 0 ? rk + sx : rk);
       }
-      const double* Ak = mA(g, b, k);
+      // tv2 = A x (tv1 keeps A x for k = 0), then + B u
+      wg::gemv<false>(nx, nx, 1.0, mA(g, b, k), nx, xk, 0.0, tv[2], sm);
+      if (k == 0)
+        for (int i = threadIdx.x; i < nx; i += NT) tv[1][i] = tv[2][i];
+      wg::gemv<false>(nx, nu, 1.0, Bk, nu, uk, 1.0, tv[2], sm);
       const double* xn = X + ((int64_t)b * N + k) * nx;
       for (int i = threadIdx.x; i < nx; i += NT) {
-        double a = 0.0, ax0 = 0.0;
-        for (int j = 0; j < nx; ++j) a = fma(Ak[(int64_t)i * nx + j], xk[j], a);
-        for (int j = 0; j < nu; ++j) a = fma(Bk[(int64_t)i * nu + j], uk[j], a);
         const double fk = g.f ? vf(g, b, k)[i] : 0.0;
-        if (k == 0) {
-          for (int j = 0; j < nx; ++j) ax0 = fma(Ak[(int64_t)i * nx + j], x0[j], ax0);
-          up(-(fk + ax0) - ((a - ax0) - xn[i]), fk + ax0);
-        } else {
-          up(-fk - (a - xn[i]), fk);
-        }
+        up(-fk - (tv[2][i] - xn[i]), k == 0 ? fk + tv[1][i] : fk);
       }
     }
-    // stationarity in x_k (k >= 1)
     if (k >= 1) {
       const double* Qk = mQ(g, b, k);
       const double* lm = LAM + ((int64_t)b * N + (k - 1)) * nx;
+      wg::gemv<false>(nx, nx, 0.5, Qk, nx, xk, 0.0, tv[0], sm);
+      wg::gemv<true>(nx, nx, 0.5, Qk, nx, xk, 1.0, tv[0], sm);
+      if (k < N) {
+        const double* uk = U + ((int64_t)b * N + k) * nu;
+        const double* lk = LAM + ((int64_t)b * N + k) * nx;
+        if (g.S) wg::gemv<true>(nu, nx, 1.0, mS(g, b, k), nx, uk, 1.0, tv[0], sm);
+        wg::gemv<true>(nx, nx, 1.0, mA(g, b, k), nx, lk, 1.0, tv[0], sm);
+      }
       for (int i = threadIdx.x; i < nx; i += NT) {
-        double a = 0.0;
-        for (int j = 0; j < nx; ++j) a = fma(0.5 * (Qk[(int64_t)i * nx + j] + Qk[(int64_t)j * nx + i]), xk[j], a);
-        if (k < N) {
-          const double* uk = U + ((int64_t)b * N + k) * nu;
-          const double* lk = LAM + ((int64_t)b * N + k) * nx;
-          const double* Ak = mA(g, b, k);
-          if (g.S) {
-            const double* Sk = mS(g, b, k);
-            for (int j = 0; j < nu; ++j) a = fma(Sk[(int64_t)j * nx + i], uk[j], a);
-          }
-          for (int j = 0; j < nx; ++j) a = fma(Ak[(int64_t)j * nx + i], lk[j], a);
-        }
         const double qk = vq(g, b, k)[i];
-        up(-qk - (a - lm[i]), qk);
+        up(-qk - (tv[0][i] - lm[i]), qk);
       }
     }
+    wg::sync();
   }
   // workgroup maxima, then atomic maxima on the bit patterns (non-negative doubles order as
   // integers; a NaN's pattern is above every number's)
-  __shared__ double red[2][NT];
-  red[0][threadIdx.x] = mr;
-  red[1][threadIdx.x] = mb;
+  sm.red[threadIdx.x] = mr;
   __syncthreads();
   for (int st = NT / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int q = 0; q < 2; ++q) {
-        const double o = red[q][threadIdx.x + st], cur = red[q][threadIdx.x];
-        red[q][threadIdx.x] = (o > cur || o != o) ? o : cur;
-      }
+    if (threadIdx.x < st) {
+      const double o = sm.red[threadIdx.x + st], cur = sm.red[threadIdx.x];
+      sm.red[threadIdx.x] = (o > cur || o != o) ? o : cur;
+    }
+    __syncthreads();
+  }
+  const double rmax = sm.red[0];
+  __syncthreads();
+  sm.red[threadIdx.x] = mb;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      const double o = sm.red[threadIdx.x + st], cur = sm.red[threadIdx.x];
+      sm.red[threadIdx.x] = (o > cur || o != o) ? o : cur;
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws + g.oAcc) + 2 * (int64_t)b;
-    atomicMax(acc, (unsigned long long)__double_as_longlong(fabs(red[0][0])));
-    atomicMax(acc + 1, (unsigned long long)__double_as_longlong(fabs(red[1][0])));
+    atomicMax(acc, (unsigned long long)__double_as_longlong(fabs(rmax)));
+    atomicMax(acc + 1, (unsigned long long)__double_as_longlong(fabs(sm.red[0])));
   }
 }
 
@@ -607,7 +606,7 @@ extern "C" int lq_pit_solve(int32_t batch, int32_t N, int32_t nx, int32_t nu, in
   const size_t lds = sizeof(wg::Smem);
   hipError_t e = hipSuccess;
   for (const void* k : {(const void*)k_pit_bwd<false>, (const void*)k_pit_bwd<true>, (const void*)k_pit_fwd<false>,
-                        (const void*)k_pit_fwd<true>})
+                        (const void*)k_pit_fwd<true>, (const void*)k_pit_resid})
     if (e == hipSuccess) e = raise_lds_limit(k, lds);
   if (e != hipSuccess) return rc_of(e, fn);
   const dim3 grid(P, batch);
@@ -620,7 +619,7 @@ extern "C" int lq_pit_solve(int32_t batch, int32_t N, int32_t nx, int32_t nu, in
   hipLaunchKernelGGL(k_pit_bwd<true>, grid, dim3(NT), lds, st, g, w);
   hipLaunchKernelGGL(k_pit_fwd<true>, grid, dim3(NT), lds, st, g, w, x, u, lam);
   hipLaunchKernelGGL(k_pit_zero_acc, dim3((2 * batch + 255) / 256), dim3(256), 0, st, g, w);
-  hipLaunchKernelGGL(k_pit_resid, dim3((N + RCH) / RCH, batch), dim3(NT), 0, st, g, x, u, lam, w);
+  hipLaunchKernelGGL(k_pit_resid, dim3((N + RCH) / RCH, batch), dim3(NT), lds, st, g, x, u, lam, w);
   hipLaunchKernelGGL(k_pit_relres, dim3((batch + 255) / 256), dim3(256), 0, st, g, w, rel_res, info);
   return rc_of(hipGetLastError(), fn);
 }

@@ -20,8 +20,10 @@ Contents (each function cites the passage of the paper it follows):
 * ``blocktri`` -- symmetric positive definite block-tridiagonal systems: dense definition, the
                   cyclic-reduction factor as the Cholesky factor of the valuation-ordered
                   matrix, the written-out CR and PCR recursions, preconditioned CG.
+* ``update``   -- the stage Hessians changed by constraint-penalty changes (low-rank terms) and
+                  the factors of the modified problem.
 
 All arithmetic is float64 with numpy / scipy (LAPACK).  Nothing here is blocked,
 fused or reordered beyond the definitions.
 """
-from . import adjoint, blocktri, closed, condense, kkt, riccati  # noqa: F401
+from . import adjoint, blocktri, closed, condense, kkt, riccati, update  # noqa: F401

@@ -16,3 +16,4 @@ from .problems import (  # noqa: F401
     stack,
 )
 from .blocktri import random_blocktri  # noqa: F401
+from .update import random_update_rows  # noqa: F401

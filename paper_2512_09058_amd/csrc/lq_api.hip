@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lq_internal.hpp"
+#include "lqupdate.h"
 
 namespace lq {
 size_t generic_factor_lds(int nx, int nu);
@@ -59,6 +60,12 @@ hipError_t prepare_tckpt(int NXP, int NUP, lq_mode mode, size_t lds);
 int tckpt_blocks_per_cu(int NXP, int NUP, lq_mode mode, size_t lds);
 hipError_t launch_solve_tckpt(int NXP, int NUP, lq_mode mode, const SolveArgs& a, size_t lds,
                               const GenericLaunch& c, hipStream_t st);
+// lq_update.hip
+int update_width(int fsmax, int nuxmax, int nxmax, int* ldy_out);
+hipError_t launch_update_data(const Desc* desc, int batch, int maxN, const lq_update& u, double* Q, double* R,
+                              double* S, hipStream_t st);
+hipError_t launch_factor_update(const Desc* desc, int batch, int fsmax, int nuxmax, int nxmax, const lq_data& d,
+                                const lq_update& u, double* F, double* V, int32_t* info, hipStream_t st);
 }  // namespace lq
 
 namespace lq {
@@ -227,7 +234,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   for (int a = 0; a < LQ_ARR_COUNT; ++a) p->off[a].resize(batch);
   p->desc_h.resize(batch);
   int64_t acc[LQ_ARR_COUNT] = {};
-  int64_t aF = 0, aV = 0, aV2 = 0, aZB = 0;
+  int64_t aF = 0, aV = 0, aV2 = 0, aZB = 0, aK = 0;
   size_t ldsf = 0, ldss = 0;
   for (int i = 0; i < batch; ++i) {
     const int64_t n = N[i], x = nx[i], u = nu[i];
@@ -253,6 +260,7 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
     D.oV = aV; aV += n * u + (n + 1) * x;
     D.oV2 = aV2; aV2 += lq::v2_elems(n, x, u);
     D.oZB = aZB; aZB += n * (2 * x + u);
+    D.oK = aK; aK += n + 1;
     ldsf = std::max(ldsf, lq::generic_factor_lds(nx[i], nu[i]));
     ldss = std::max(ldss, lq::generic_solve_lds(nx[i], nu[i]));
     p->stage_doubles = std::max(p->stage_doubles, lq::generic_stage_doubles(nx[i], nu[i]));
@@ -683,6 +691,60 @@ extern "C" int lq_solve_backward(const lq_plan* p, const lq_data* d, void* ws, c
   g.gA = gA; g.gB = gB; g.gQ = gQ; g.gR = gR; g.gS = gS; g.gq = gq; g.gr = gr; g.gf = gf; g.gx0 = gx0;
   e = lq::launch_grad_generic(g, st);
   return launch_status(e, "lq_solve_backward");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Factorisation updates (lqupdate.h).
+static int check_update_rows(const lq_plan* p, const lq_update* u, const char* fn) {
+  if (!u || u->m == 0) return LQ_OK;
+  if (u->m < 0 || u->m > LQ_UPDATE_MAX_ROWS)
+    return fail(LQ_EINVAL, "%s: m = %d outside 0..%d", fn, u->m, LQ_UPDATE_MAX_ROWS);
+  if (!u->C || !u->D || !u->dsig) return fail(LQ_EINVAL, "%s: C, D and dsig are required when m > 0", fn);
+  return LQ_OK;
+}
+
+static int update_fsmax(const lq_plan* p) {
+  int64_t fs = 0;
+  for (int i = 0; i < p->batch; ++i) fs = std::max(fs, lq::stage_factor_elems(p->nx[i], p->nu[i]));
+  return (int)std::min<int64_t>(fs, 1 << 30);
+}
+
+extern "C" int32_t lq_update_max_columns(const lq_plan* p) {
+  if (!p) return 0;
+  return lq::update_width(update_fsmax(p), p->maxnx + p->maxnu, p->maxnx, nullptr);
+}
+
+extern "C" int lq_update_data(const lq_plan* p, const lq_update* u, double* Q, double* R, double* S,
+                              hipStream_t st) {
+  g_err.clear();
+  const char* fn = "lq_update_data";
+  if (!p) return fail(LQ_EINVAL, "%s: plan is NULL", fn);
+  int rc = check_update_rows(p, u, fn);
+  if (rc) return rc;
+  if (!Q || !R || !S) return fail(LQ_EINVAL, "%s: Q, R and S are required", fn);
+  if (!u || u->m == 0) return LQ_OK;
+  return launch_status(lq::launch_update_data(p->desc_d, p->batch, p->maxN, *u, Q, R, S, st), fn);
+}
+
+extern "C" int lq_factor_update(const lq_plan* p, const lq_data* d, const lq_update* u, void* ws, int32_t* info,
+                                hipStream_t st) {
+  g_err.clear();
+  const char* fn = "lq_factor_update";
+  int rc = check_common(p, d, ws, fn);
+  if (rc) return rc;
+  if (!info) return fail(LQ_EINVAL, "%s: info is NULL", fn);
+  if ((rc = check_update_rows(p, u, fn))) return rc;
+  if (p->mode != LQ_F64 || p->ckpt != 0)
+    return fail(LQ_EUNSUPPORTED, "%s: updates need a float64 plan without checkpoints", fn);
+  const int fsmax = update_fsmax(p);
+  if (lq::update_width(fsmax, p->maxnx + p->maxnu, p->maxnx, nullptr) <= 0)
+    return fail(LQ_EUNSUPPORTED, "%s: a stage of this plan does not fit the update kernel's LDS", fn);
+  lq_update none = {0, nullptr, nullptr, nullptr};
+  char* w = (char*)ws;
+  return launch_status(lq::launch_factor_update(p->desc_d, p->batch, fsmax, p->maxnx + p->maxnu, p->maxnx, *d,
+                                                u ? *u : none, (double*)(w + p->offF), (double*)(w + p->offV),
+                                                info, st),
+                       fn);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -17,6 +17,7 @@ struct Desc {
   int64_t oV;   // rbar (N nu) then p ((N+1) nx), float64: sweep of lq_factor's right-hand side
   int64_t oV2;  // refinement / adjoint state, float64 (layout: v2_* below)
   int64_t oZB;  // adjoint solution: xbar (N nx), ubar (N nu), lambar (N nx), float64
+  int64_t oK;   // stages (N + 1) of the instances before this one (per-stage arrays of updates)
 };
 
 // Factor block of one stage (elements): [LR packed lower, nu(nu+1)/2][1/diag LR, nu]

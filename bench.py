@@ -793,6 +793,123 @@ def bench_blocktri(args):
     print(json.dumps(out))
 
 
+def update_flops(dsig, N, nx, nu):
+    """Algorithmic float64 flops of one factor update (hyperbolic Householder steps and the products
+    forming Upsilon) from the per-stage counts of nonzero rows: with W_k the nonzero rows of stages
+    k..N, stage N's L^Q step and stage k's input and state steps cost 4 W per row per pivot, the
+    products for stage k-1 2 (nx + nu) nx W_k."""
+    nux = nx + nu
+    nz = (dsig != 0).sum(axis=-1)                       # [batch, N+1]
+    W = np.cumsum(nz[:, ::-1], axis=1)[:, ::-1]         # W[:, k] = rows of stages k..N
+    rows_u = sum(nux - i for i in range(nu))
+    rows_x = sum(nx - i for i in range(nx))
+    fl = 4.0 * W[:, N] * rows_x + 2.0 * nux * nx * W[:, N]
+    fl = fl + (4.0 * W[:, :N] * rows_u).sum(axis=1)
+    fl = fl + (4.0 * W[:, 1:N] * rows_x + 2.0 * nux * nx * W[:, 1:N]).sum(axis=1)
+    return float(fl.sum())
+
+
+UPDATE_SHAPES = {"update4096": (4096, 50, 12, 4, 0.08), "update1024x60": (1024, 64, 60, 15, 0.06)}
+
+
+def bench_update(args):
+    """Factorisation updates, float64: every instance gets a few active-set changes per step (box
+    rows, two per stage, each changed with a probability chosen for about 8 changes per instance),
+    applied as penalty updates and, on the next step, removed again (downdates).  Timed per step:
+    the data modification, the factor update and a solve, beside a refactorisation of the same
+    modified data and the same solve.  Shapes: the batch-4096 workload (N = 50, nx = 12, nu = 4),
+    where the rank of the change is close to nx, and a mass-spring-sized state (1024 instances,
+    N = 64, nx = 60, nu = 15: 30 masses, a quarter of them actuated), where it is far below."""
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    from paper_2512_09058_amd import update as U
+    from oracle import riccati, update as oupd
+    batch, N, nx, nu, density = UPDATE_SHAPES[args.workload]
+    m = 2
+    prob = synth.make_batch(2) if args.workload == "update4096" else synth.make_batch(2, batch, N=N, nx=nx, nu=nu)
+    data = L.pack(prob)
+    plan = L.Plan(N, nx, nu, batch=batch, mode="f64")
+    data["S"] = torch.zeros(plan.totals["S"], dtype=torch.float64, device="cuda")
+    ws = plan.workspace()
+    info = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    x, u, lam = plan.empty_outputs()
+    rel = torch.zeros(batch, dtype=torch.float64, device="cuda")
+    C, D, dsig = synth.random_update_rows(31, batch, N, nx, nu, m, density=density)
+    rows = [U.pack_rows(C, D, dsig), U.pack_rows(C, D, -dsig)]
+    uws = U.workspace(plan)
+    L.factor(plan, data, ws, info)
+    stream = torch.cuda.current_stream()
+    keys = ["update_data", "factor_update", "solve_after_update", "factor", "solve_after_factor"]
+    t = {k: [] for k in keys}
+    bad = 0
+    for s_ in range(args.warmup + args.steps):
+        rw = rows[s_ % 2]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        e[0].record(stream)
+        U.update_data(plan, rw, data, stream=stream)
+        e[1].record(stream)
+        U.factor_update(plan, data, rw, ws, info, uws, stream=stream)
+        e[2].record(stream)
+        L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=1e-10, max_it=0, check_res=True, stream=stream)
+        e[3].record(stream)
+        L.factor(plan, data, ws, info, stream=stream)
+        e[4].record(stream)
+        L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=1e-10, max_it=0, check_res=True, stream=stream)
+        e[5].record(stream)
+        if s_ >= args.warmup:
+            for i, k in enumerate(keys):
+                t[k].append((e[i], e[i + 1]))
+        if s_ == args.warmup + args.steps - 1:
+            torch.cuda.synchronize()
+            bad = int((info != 0).sum().item())
+    torch.cuda.synchronize()
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in t.items()}
+    ms_upd = ms["update_data"] + ms["factor_update"]
+    # the last step's state: modified when the step count is odd
+    modified = (args.warmup + args.steps) % 2 == 1
+    errs = []
+    for i in (0, batch - 1):
+        p = prob.instance(i)
+        q = oupd.modified_problem(p, C[i], D[i], dsig[i]) if modified else p
+        ref = riccati.solve(q)
+        sol = tuple(L.unpack(plan, n_, a_, i) for n_, a_ in (("x", x), ("u", u), ("lam", lam)))
+        errs.append(max(np.abs(a - b).max() for a, b in zip(sol, ref)) / max(np.abs(b).max() for b in ref))
+    fl = update_flops(dsig, N, nx, nu)
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        cnt = 0
+        while time.perf_counter() - t0 < 10.0 and cnt < batch:
+            q = oupd.modified_problem(prob.instance(cnt), C[cnt], D[cnt], dsig[cnt])
+            riccati.solve(q)
+            cnt += 1
+        tc = (time.perf_counter() - t0) / cnt
+        cpu = {"value": 1.0 / tc, "unit": "solves/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{cnt} instances: the oracle's modified problem and its Riccati solve (numpy float64, one "
+                         f"process), {tc * 1e6:.0f} us per instance"}
+    nz = (dsig != 0).sum(axis=(1, 2))
+    out = {"metric": f"LQ KKT solves/s after a low-rank active-set change, batch {batch} nx={nx} nu={nu} N={N} "
+                     "(factor update + solve)",
+           "value": batch / ((ms_upd + ms["solve_after_update"]) * 1e-3), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_upd + ms["solve_after_update"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (workload-2 generators; seeded box-constraint rows, penalty changes U(0.5, 2))",
+           "config": {"workload": f"batch {batch}, N={N}, nx={nx}, nu={nu}, update rows m={m} per stage, "
+                                  f"density {density}",
+                      "batch": batch, "N": N, "nx": nx, "nu": nu, "rows_per_instance_mean": float(nz.mean()),
+                      "rows_per_instance_max": int(nz.max()), "max_columns": U.max_columns(plan)},
+           "ms": ms, "refactor_solves_per_s": batch / ((ms["factor"] + ms["solve_after_factor"]) * 1e-3),
+           "update_over_refactor_factorisation_speedup": ms["factor"] / ms_upd,
+           "info_nonzero": bad, "fwd_err_vs_oracle_sampled": max(errs),
+           "roofline": {"bound": "alu", "kernel": "k_factor_update", "achieved": fl / (ms["factor_update"] * 1e-3) / 1e12,
+                        "peak": 78.6, "unit": "TFLOP/s", "frac": fl / (ms["factor_update"] * 1e-3) / 1e12 / 78.6,
+                        "traffic": None, "algorithmic_flops_per_launch": fl, "ms_per_launch": ms["factor_update"]},
+           "cpu_baseline": cpu}
+    print(f"[bench] update: {ms}", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -806,7 +923,8 @@ def main():
                          "(0: all distinct)")
     ap.add_argument("--pit-intervals", type=int, nargs="*", default=[4, 8, 16],
                     help="large workload: interval counts of the parallel-in-time path")
-    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20", "blocktri"],
+    ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20", "blocktri",
+                                           "update4096", "update1024x60"],
                     default="batch4096",
                     help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
                          "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")
@@ -846,6 +964,8 @@ def main():
         return bench_single(args)
     if args.workload == "blocktri":
         return bench_blocktri(args)
+    if args.workload in UPDATE_SHAPES:
+        return bench_update(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)

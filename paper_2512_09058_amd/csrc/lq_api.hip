@@ -61,11 +61,15 @@ int tckpt_blocks_per_cu(int NXP, int NUP, lq_mode mode, size_t lds);
 hipError_t launch_solve_tckpt(int NXP, int NUP, lq_mode mode, const SolveArgs& a, size_t lds,
                               const GenericLaunch& c, hipStream_t st);
 // lq_update.hip
-int update_width(int fsmax, int nuxmax, int nxmax, int* ldy_out);
+int update_width(int lrsmax, int lqmax, int nuxmax, int nxmax, int* ldy_out);
+bool update_sweep_fits(int fsmax, int nuxmax, int nxmax);
+void update_ws_layout(int wmax, int64_t sum_Nnx, int64_t sum_K, int batch, size_t* oSg, size_t* oWk, size_t* oSt,
+                      size_t* total);
 hipError_t launch_update_data(const Desc* desc, int batch, int maxN, const lq_update& u, double* Q, double* R,
                               double* S, hipStream_t st);
-hipError_t launch_factor_update(const Desc* desc, int batch, int fsmax, int nuxmax, int nxmax, const lq_data& d,
-                                const lq_update& u, double* F, double* V, int32_t* info, hipStream_t st);
+hipError_t launch_factor_update(const Desc* desc, int batch, int maxN, int lrsmax, int lqmax, int fsmax, int nuxmax,
+                                int nxmax, int64_t sum_Nnx, int64_t sum_K, const lq_data& d, const lq_update& u,
+                                double* F, double* V, void* uws, int32_t* info, hipStream_t st);
 }  // namespace lq
 
 namespace lq {
@@ -703,15 +707,36 @@ static int check_update_rows(const lq_plan* p, const lq_update* u, const char* f
   return LQ_OK;
 }
 
-static int update_fsmax(const lq_plan* p) {
-  int64_t fs = 0;
-  for (int i = 0; i < p->batch; ++i) fs = std::max(fs, lq::stage_factor_elems(p->nx[i], p->nu[i]));
-  return (int)std::min<int64_t>(fs, 1 << 30);
+// Largest stage pieces of a plan for the update kernels: L^R + 1/diag + L^S, L^Q + 1/diag, the
+// whole block; and the sums of N nx and N + 1 over the instances.
+struct UpdSizes {
+  int lrs = 0, lq = 0, fs = 0;
+  int64_t sum_Nnx = 0, sum_K = 0;
+  int wmax = 0;
+};
+static UpdSizes update_sizes(const lq_plan* p) {
+  UpdSizes z;
+  for (int i = 0; i < p->batch; ++i) {
+    const int64_t x = p->nx[i], u = p->nu[i];
+    z.lrs = (int)std::max<int64_t>(z.lrs, std::min<int64_t>(u * (u + 1) / 2 + u + x * u, 1 << 30));
+    z.lq = (int)std::max<int64_t>(z.lq, std::min<int64_t>(x * (x + 1) / 2 + x, 1 << 30));
+    z.fs = (int)std::max<int64_t>(z.fs, std::min<int64_t>(lq::stage_factor_elems(x, u), 1 << 30));
+    z.sum_Nnx += (int64_t)p->N[i] * x;
+    z.sum_K += (int64_t)p->N[i] + 1;
+  }
+  z.wmax = lq::update_width(z.lrs, z.lq, p->maxnx + p->maxnu, p->maxnx, nullptr);
+  return z;
 }
 
-extern "C" int32_t lq_update_max_columns(const lq_plan* p) {
+extern "C" int32_t lq_update_max_columns(const lq_plan* p) { return p ? update_sizes(p).wmax : 0; }
+
+extern "C" size_t lq_update_workspace_bytes(const lq_plan* p) {
   if (!p) return 0;
-  return lq::update_width(update_fsmax(p), p->maxnx + p->maxnu, p->maxnx, nullptr);
+  const UpdSizes z = update_sizes(p);
+  if (z.wmax <= 0) return 0;
+  size_t oSg, oWk, oSt, tot;
+  lq::update_ws_layout(z.wmax, z.sum_Nnx, z.sum_K, p->batch, &oSg, &oWk, &oSt, &tot);
+  return tot;
 }
 
 extern "C" int lq_update_data(const lq_plan* p, const lq_update* u, double* Q, double* R, double* S,
@@ -726,8 +751,8 @@ extern "C" int lq_update_data(const lq_plan* p, const lq_update* u, double* Q, d
   return launch_status(lq::launch_update_data(p->desc_d, p->batch, p->maxN, *u, Q, R, S, st), fn);
 }
 
-extern "C" int lq_factor_update(const lq_plan* p, const lq_data* d, const lq_update* u, void* ws, int32_t* info,
-                                hipStream_t st) {
+extern "C" int lq_factor_update(const lq_plan* p, const lq_data* d, const lq_update* u, void* ws, void* uws,
+                                int32_t* info, hipStream_t st) {
   g_err.clear();
   const char* fn = "lq_factor_update";
   int rc = check_common(p, d, ws, fn);
@@ -736,14 +761,18 @@ extern "C" int lq_factor_update(const lq_plan* p, const lq_data* d, const lq_upd
   if ((rc = check_update_rows(p, u, fn))) return rc;
   if (p->mode != LQ_F64 || p->ckpt != 0)
     return fail(LQ_EUNSUPPORTED, "%s: updates need a float64 plan without checkpoints", fn);
-  const int fsmax = update_fsmax(p);
-  if (lq::update_width(fsmax, p->maxnx + p->maxnu, p->maxnx, nullptr) <= 0)
-    return fail(LQ_EUNSUPPORTED, "%s: a stage of this plan does not fit the update kernel's LDS", fn);
+  const UpdSizes z = update_sizes(p);
+  const bool rows = u && u->m > 0;
+  if (!lq::update_sweep_fits(z.fs, p->maxnx + p->maxnu, p->maxnx) || (rows && z.wmax <= 0))
+    return fail(LQ_EUNSUPPORTED, "%s: a stage of this plan does not fit the update kernels' LDS", fn);
+  if (rows && !uws) return fail(LQ_EINVAL, "%s: the update workspace is required with update rows", fn);
+  if (rows && p->batch > 65535) return fail(LQ_EUNSUPPORTED, "%s: at most 65535 instances with update rows", fn);
+  if (rows && (((uintptr_t)uws) & 255)) return fail(LQ_EINVAL, "%s: update workspace must be 256-byte aligned", fn);
   lq_update none = {0, nullptr, nullptr, nullptr};
   char* w = (char*)ws;
-  return launch_status(lq::launch_factor_update(p->desc_d, p->batch, fsmax, p->maxnx + p->maxnu, p->maxnx, *d,
-                                                u ? *u : none, (double*)(w + p->offF), (double*)(w + p->offV),
-                                                info, st),
+  return launch_status(lq::launch_factor_update(p->desc_d, p->batch, p->maxN, z.lrs, z.lq, z.fs, p->maxnx + p->maxnu,
+                                                p->maxnx, z.sum_Nnx, z.sum_K, *d, rows ? *u : none,
+                                                (double*)(w + p->offF), (double*)(w + p->offV), uws, info, st),
                        fn);
 }
 

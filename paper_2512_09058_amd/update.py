@@ -45,6 +45,14 @@ def max_columns(plan: Plan) -> int:
     return int(_lib.load().lq_update_max_columns(plan.handle))
 
 
+def workspace(plan: Plan, device="cuda") -> torch.Tensor:
+    """The update workspace lq_factor_update needs with update rows."""
+    n = int(_lib.load().lq_update_workspace_bytes(plan.handle))
+    if n == 0:
+        raise ValueError("this plan's stages do not fit the update kernels")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
 def update_data(plan: Plan, rows: Dict[str, torch.Tensor], data: Dict[str, torch.Tensor], stream=None):
     """Applies the rows' penalty changes to data["Q"], data["R"], data["S"] in place."""
     u = _upd(rows)
@@ -53,10 +61,11 @@ def update_data(plan: Plan, rows: Dict[str, torch.Tensor], data: Dict[str, torch
 
 
 def factor_update(plan: Plan, data: Dict[str, torch.Tensor], rows: Optional[Dict[str, torch.Tensor]],
-                  ws: torch.Tensor, info: torch.Tensor, stream=None):
+                  ws: torch.Tensor, info: torch.Tensor, uws: Optional[torch.Tensor] = None, stream=None):
     """Updates the factors in ws to those of `data` (already modified) and recomputes the
-    right-hand-side sweep; rows=None only recomputes the sweep (new q, r, f)."""
+    right-hand-side sweep; rows=None only recomputes the sweep (new q, r, f).  uws: the update
+    workspace (`workspace(plan)`), required with rows."""
     dd = _data(data)
     u = _upd(rows)
-    check(_lib.load().lq_factor_update(plan.handle, C.byref(dd), C.byref(u), _ptr(ws), _ptr(info), _stream(stream)),
-          "lq_factor_update")
+    check(_lib.load().lq_factor_update(plan.handle, C.byref(dd), C.byref(u), _ptr(ws), _ptr(uws), _ptr(info),
+                                       _stream(stream)), "lq_factor_update")

@@ -90,7 +90,7 @@ def _rows(insts, seed, m, density=0.5, box=True, sigma=(0.5, 2.0)):
 def _check_update(plan, data, ws, info, insts, Cs, Ds, ss, label, sample=None):
     rows = U.pack_rows(Cs, Ds, ss)
     U.update_data(plan, rows, data)
-    U.factor_update(plan, data, rows, ws, info)
+    U.factor_update(plan, data, rows, ws, info, U.workspace(plan))
     res = _solve(plan, data, ws, info)
     assert np.all(res["info"] == 0), (label, res["info"])
     assert np.all(res["rel"] <= 1e-10), (label, res["rel"].max())
@@ -115,7 +115,8 @@ def _check_update(plan, data, ws, info, insts, Cs, Ds, ss, label, sample=None):
 
 
 CASES = [("small", 12, 4, 20, 2, True), ("small", 6, 2, 15, 3, False), ("tile", 12, 4, 17, 2, True),
-         ("tile", 20, 5, 12, 1, False), ("generic", 12, 4, 9, 2, True), ("generic", 33, 7, 8, 2, False)]
+         ("tile", 20, 5, 12, 1, False), ("tile", 60, 15, 6, 2, True), ("generic", 12, 4, 9, 2, True),
+         ("generic", 33, 7, 8, 2, False)]
 
 
 @pytest.mark.parametrize("variant,nx,nu,N,m,box", CASES)
@@ -187,7 +188,7 @@ def test_rank_limit_leaves_instance_untouched():
     assert np.count_nonzero(ss[1]) > cols
     before = ws.clone()
     rows = U.pack_rows(Cs, Ds, ss)
-    U.factor_update(plan, data, rows, ws, info)
+    U.factor_update(plan, data, rows, ws, info, U.workspace(plan))
     got = info.cpu().numpy()
     assert got[0] == 0 and got[1] == U.LQ_INFO_UPDATE_RANK and got[2] == 0, got
     views_b = workspace_views({"plan": plan, "ws": before})
@@ -213,7 +214,7 @@ def test_indefinite_downdate_reports_stage():
     assert np.linalg.eigvalsh(kkt.sym(mod.R[j]))[0] < 0
     rows = U.pack_rows(Cs, Ds, ss)
     U.update_data(plan, rows, data)
-    U.factor_update(plan, data, rows, ws, info)
+    U.factor_update(plan, data, rows, ws, info, U.workspace(plan))
     torch.cuda.synchronize()
     got = info.cpu().numpy()
     assert got[0] == j + 1 and got[1] == 0, got
@@ -227,13 +228,15 @@ def test_refusals():
     rows = U.pack_rows(Cs, Ds, ss)
     bad = dict(rows, m=U.LQ_UPDATE_MAX_ROWS + 1)
     with pytest.raises(RuntimeError, match="outside"):
-        U.factor_update(plan, data, bad, ws, info)
+        U.factor_update(plan, data, bad, ws, info, U.workspace(plan))
     mixed = L.Plan(5, 4, 2, batch=2, mode="mixed_f32")
     with pytest.raises(RuntimeError, match="float64 plan"):
-        U.factor_update(mixed, data, rows, mixed.workspace(), info)
+        U.factor_update(mixed, data, rows, mixed.workspace(), info, U.workspace(plan))
     ck = L.Plan(5, 4, 2, batch=2, mode="f64", ckpt_stride=2)
     with pytest.raises(RuntimeError, match="float64 plan"):
-        U.factor_update(ck, data, rows, ck.workspace(), info)
+        U.factor_update(ck, data, rows, ck.workspace(), info, U.workspace(plan))
+    with pytest.raises(RuntimeError, match="update workspace"):
+        U.factor_update(plan, data, rows, ws, info, None)
     nos = {k: v for k, v in data.items() if k != "S"}
     with pytest.raises((RuntimeError, KeyError)):
         U.update_data(plan, rows, nos)

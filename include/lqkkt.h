@@ -117,6 +117,18 @@ int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx, const int
                    lq_mode mode, int32_t ckpt_stride, lq_plan** out);
 void lq_plan_destroy(lq_plan* plan);
 
+/* A plan over the instances idx[0..n) (host array, distinct indices into the parent's batch) that
+ * reads and writes the PARENT's packed arrays: its data (A, B, Q, ...) and its outputs x, u, lam at
+ * the parent's offsets, so a subset can be factored and solved again in place, e.g. in float64 after
+ * a mixed-precision solve reported info != 0 for those instances (the stage matrix lost positive
+ * definiteness in float32 products, or refinement did not converge; the float64 fallback of the
+ * mixed path).  Its own workspace (lq_plan_workspace_bytes) and its per-instance status arrays
+ * (info, rel_res, iters: n entries, entry i for instance idx[i]) are separate.  Uses the tile or
+ * general kernels (the size-specialised ones address instances by batch position).  The parent may
+ * be destroyed afterwards. */
+int lq_plan_create_subset(const lq_plan* parent, int32_t n, const int32_t* idx, lq_mode mode,
+                          int32_t ckpt_stride, lq_plan** out);
+
 /* Bytes of device workspace the caller provides to lq_factor / lq_solve / lq_solve_backward
  * (holds the factors, the backward-sweep vectors and refinement state).  256-byte aligned
  * pointers are required. */

@@ -31,6 +31,8 @@ EXPORTS = {
     "lq_plan_create": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32), C.c_int, C.c_int32, C.POINTER(C.c_void_p)]),
     "lq_plan_destroy": (None, [C.c_void_p]),
+    "lq_plan_create_subset": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int, C.c_int32,
+                                        C.POINTER(C.c_void_p)]),
     "lq_plan_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "lq_plan_offsets": (C.c_int64, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
     "lq_plan_variant": (C.c_char_p, [C.c_void_p]),

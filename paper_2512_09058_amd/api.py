@@ -56,6 +56,10 @@ class Plan:
         ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
         check(lib.lq_plan_create(self.batch, ip(Ns), ip(nxs), ip(nus), MODES[mode], int(ckpt_stride),
                                  C.byref(self._h)), "lq_plan_create")
+        self._describe()
+
+    def _describe(self):
+        lib = _lib.load()
         self.workspace_bytes = int(lib.lq_plan_workspace_bytes(self._h))
         self.variant = lib.lq_plan_variant(self._h).decode()
         self.offsets: Dict[str, np.ndarray] = {}
@@ -77,6 +81,23 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def subset(self, idx, mode: str = "f64", ckpt_stride: int = 0) -> "Plan":
+        """lq_plan_create_subset: a plan over instances idx of this batch that reads and writes this
+        plan's packed arrays (data and x, u, lam); its status arrays have len(idx) entries."""
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1))
+        sub = Plan.__new__(Plan)
+        sub._h = C.c_void_p()
+        check(_lib.load().lq_plan_create_subset(self._h, int(idx.size), idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                MODES[mode], int(ckpt_stride), C.byref(sub._h)),
+              "lq_plan_create_subset")
+        sub.batch = int(idx.size)
+        sub.N, sub.nx, sub.nu = self.N[idx], self.nx[idx], self.nu[idx]
+        sub.mode = mode
+        sub.ckpt_stride = int(ckpt_stride)
+        sub.parent_index = idx
+        sub._describe()
+        return sub
 
     def set_variant(self, name: str):
         """Select the factor kernel variant ("small", "tile" or "generic"; see lq_plan_set_variant)."""
@@ -133,6 +154,39 @@ def solve(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, lam
     o = LqSolveOpts(float(tol), int(max_it), int(bool(check_res)))
     check(lib.lq_solve(plan.handle, C.byref(dd), _ptr(ws), C.byref(o), _ptr(x), _ptr(u), _ptr(lam),
                        _ptr(rel_res), _ptr(iters), _ptr(info), _stream(stream)), "lq_solve")
+
+
+def solve_with_fallback(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, lam, rel_res, iters,
+                        info, tol: float = 1e-10, max_it: int = 10, fallback_max_it: int = 2, stream=None) -> np.ndarray:
+    """Factor + solve with the plan's precision, then factor and solve again in float64 every instance
+    whose info is not 0 (a stage matrix that lost positive definiteness with float32 products, a
+    refinement that stopped above tol, a non-finite residual).  The float64 subset plan reads the
+    same data and writes x, u, lam in place; its info, rel_res and iters replace those of the
+    instances it solved.  Returns the indices of those instances.  (Orchestration only: every step
+    runs in the library's kernels; the one host synchronisation reads info.)"""
+    factor(plan, data, ws, info, stream=stream)
+    solve(plan, data, ws, x, u, lam, rel_res, iters, info, tol=tol, max_it=max_it, check_res=True, stream=stream)
+    if isinstance(stream, torch.cuda.Stream):
+        torch.cuda.current_stream().wait_stream(stream)
+    bad = torch.nonzero(info != 0).reshape(-1).cpu().numpy().astype(np.int32)
+    if bad.size == 0 or plan.mode == "f64":
+        return bad[:0]
+    sub = plan.subset(bad, "f64")
+    ws2 = sub.workspace(device=info.device)
+    dev = info.device
+    info2 = torch.zeros(sub.batch, dtype=torch.int32, device=dev)
+    rel2 = torch.zeros(sub.batch, dtype=torch.float64, device=dev)
+    it2 = torch.zeros(sub.batch, dtype=torch.int32, device=dev)
+    factor(sub, data, ws2, info2, stream=stream)
+    solve(sub, data, ws2, x, u, lam, rel2, it2, info2, tol=tol, max_it=fallback_max_it, check_res=True, stream=stream)
+    ib = torch.from_numpy(bad.astype(np.int64)).to(dev)
+    info.index_copy_(0, ib, info2)
+    if rel_res is not None:
+        rel_res.index_copy_(0, ib, rel2)
+    if iters is not None:
+        iters.index_copy_(0, ib, it2)
+    torch.cuda.synchronize(dev)  # the subset plan's workspace and tables are released on return
+    return bad
 
 
 def solve_backward(plan: Plan, data: Dict[str, torch.Tensor], ws: torch.Tensor, x, u, lam, gx, gu,

@@ -443,6 +443,52 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   return LQ_OK;
 }
 
+extern "C" int lq_plan_create_subset(const lq_plan* parent, int32_t n, const int32_t* idx, lq_mode mode,
+                                     int32_t ckpt_stride, lq_plan** out) {
+  g_err.clear();
+  const char* fn = "lq_plan_create_subset";
+  if (!out) return fail(LQ_EINVAL, "%s: out is NULL", fn);
+  *out = nullptr;
+  if (!parent || !idx) return fail(LQ_EINVAL, "%s: parent and idx are required", fn);
+  if (n <= 0 || n > parent->batch) return fail(LQ_EINVAL, "%s: n = %d outside 1..%d", fn, n, parent->batch);
+  std::vector<char> seen(parent->batch, 0);
+  std::vector<int32_t> N(n), nx(n), nu(n);
+  for (int i = 0; i < n; ++i) {
+    const int j = idx[i];
+    if (j < 0 || j >= parent->batch) return fail(LQ_EINVAL, "%s: idx[%d] = %d outside the parent's batch", fn, i, j);
+    if (seen[j]) return fail(LQ_EINVAL, "%s: instance %d listed twice", fn, j);
+    seen[j] = 1;
+    N[i] = parent->N[j];
+    nx[i] = parent->nx[j];
+    nu[i] = parent->nu[j];
+  }
+  lq_plan* p = nullptr;
+  int rc = lq_plan_create(n, N.data(), nx.data(), nu.data(), mode, ckpt_stride, &p);
+  if (rc) return rc;
+  // the instances live in the parent's arrays: take over its data and output offsets
+  for (int i = 0; i < n; ++i) {
+    Desc& D = p->desc_h[i];
+    const Desc& P = parent->desc_h[idx[i]];
+    D.oA = P.oA; D.oB = P.oB; D.oQ = P.oQ; D.oR = P.oR; D.oS = P.oS; D.oq = P.oq; D.or_ = P.or_; D.of = P.of;
+    D.ox0 = P.ox0; D.ox = P.ox; D.ou = P.ou; D.olam = P.olam; D.oK = P.oK;
+    for (int a = 0; a < LQ_ARR_COUNT; ++a) p->off[a][i] = parent->off[a][idx[i]];
+  }
+  for (int a = 0; a < LQ_ARR_COUNT; ++a) p->total[a] = parent->total[a];
+  p->can_small = false;
+  if (p->variant == VAR_SMALL) p->variant = p->can_tile ? VAR_TILE : VAR_GENERIC;
+  if (p->variant == VAR_GENERIC && !p->can_generic) {
+    lq_plan_destroy(p);
+    return fail(LQ_EUNSUPPORTED, "%s: no descriptor-addressed kernel takes these sizes", fn);
+  }
+  update_grids(p);
+  if (hipMemcpy(p->desc_d, p->desc_h.data(), sizeof(Desc) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    lq_plan_destroy(p);
+    return fail(LQ_EHIP, "%s: descriptor upload failed", fn);
+  }
+  *out = p;
+  return LQ_OK;
+}
+
 extern "C" int lq_plan_set_launch(lq_plan* p, const lq_launch* c) {
   g_err.clear();
   if (!p || !c) return fail(LQ_EINVAL, "lq_plan_set_launch: plan and cfg are required");

@@ -22,8 +22,11 @@ Contents (each function cites the passage of the paper it follows):
                   matrix, the written-out CR and PCR recursions, preconditioned CG.
 * ``update``   -- the stage Hessians changed by constraint-penalty changes (low-rank terms) and
                   the factors of the modified problem.
+* ``qp``       -- box-constrained LQ QPs: the optimality certificate, the augmented-Lagrangian merit
+                  function and its exact line search (sorted breakpoints), the proximal ALM with
+                  semismooth Newton inner solves.
 
 All arithmetic is float64 with numpy / scipy (LAPACK).  Nothing here is blocked,
 fused or reordered beyond the definitions.
 """
-from . import adjoint, blocktri, closed, condense, kkt, riccati, update  # noqa: F401
+from . import adjoint, blocktri, closed, condense, kkt, qp, riccati, update  # noqa: F401

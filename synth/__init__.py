@@ -17,3 +17,4 @@ from .problems import (  # noqa: F401
 )
 from .blocktri import random_blocktri  # noqa: F401
 from .update import random_update_rows  # noqa: F401
+from .massspring import mass_spring  # noqa: F401

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lq_internal.hpp"
+#include "lq_qp.hpp"
 #include "lqupdate.h"
 
 namespace lq {
@@ -820,6 +821,77 @@ extern "C" int lq_factor_update(const lq_plan* p, const lq_data* d, const lq_upd
                                                 p->maxnx, z.sum_Nnx, z.sum_K, *d, rows ? *u : none,
                                                 (double*)(w + p->offF), (double*)(w + p->offV), uws, info, st),
                        fn);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Box-constrained QPs (lqqp.h): the outer and inner loops on the host, one synchronisation per
+// inner step (the loops end when no instance is still iterating).
+static void qp_totals(const lq_plan* p, int64_t* tot, int64_t* sumK) {
+  const lq_array arr[10] = {LQ_ARR_Q, LQ_ARR_R, LQ_ARR_S, LQ_ARR_q, LQ_ARR_r, LQ_ARR_f, LQ_ARR_x0,
+                            LQ_ARR_x, LQ_ARR_u, LQ_ARR_lam};
+  for (int i = 0; i < 10; ++i) tot[i] = p->total[arr[i]];
+  int64_t k = 0;
+  for (int i = 0; i < p->batch; ++i) k += (int64_t)p->N[i] + 1;
+  *sumK = k;
+}
+
+extern "C" size_t lq_qp_workspace_bytes(const lq_plan* p, int32_t m) {
+  if (!p || m <= 0) return 0;
+  int64_t tot[10], sumK;
+  qp_totals(p, tot, &sumK);
+  return lq::qp_layout(tot, sumK, p->batch, m).total;
+}
+
+extern "C" int lq_qp_solve(const lq_plan* p, const lq_data* d, const lq_qp_constraints* c, const lq_qp_opts* o,
+                           void* pws, void* qws, double* x, double* u, double* lam, double* y, int32_t* status,
+                           int32_t* iters, hipStream_t st) {
+  g_err.clear();
+  const char* fn = "lq_qp_solve";
+  int rc = check_common(p, d, pws, fn);
+  if (rc) return rc;
+  if (!c || !o) return fail(LQ_EINVAL, "%s: constraints and options are required", fn);
+  if (c->m <= 0 || c->m > 256 || !c->C || !c->D || !c->bl || !c->bu)
+    return fail(LQ_EINVAL, "%s: m in 1..256 and C, D, bl, bu are required", fn);
+  if (!qws || (((uintptr_t)qws) & 255)) return fail(LQ_EINVAL, "%s: a 256-byte aligned QP workspace is required", fn);
+  if (!x || !u || !lam || !y || !status || !iters) return fail(LQ_EINVAL, "%s: x, u, lam, y, status, iters are required", fn);
+  if (p->mode != LQ_F64 || p->ckpt != 0) return fail(LQ_EUNSUPPORTED, "%s: a float64 plan without checkpoints is required", fn);
+  if (p->maxnx > 256) return fail(LQ_EUNSUPPORTED, "%s: nx <= 256", fn);
+  if (!(o->sigma0 > 0) || !(o->gamma > 0) || !(o->eps > 0) || o->max_outer <= 0 || o->max_inner <= 0)
+    return fail(LQ_EINVAL, "%s: sigma0, gamma, eps, max_outer, max_inner must be positive", fn);
+  int64_t tot[10], sumK;
+  qp_totals(p, tot, &sumK);
+  const lq::QPLayout L = lq::qp_layout(tot, sumK, p->batch, c->m);
+  lq::QPArgs a = lq::qp_args(p->desc_d, p->batch, c->m, *d, *c, *o, qws, L, x, u, y);
+  char* w = (char*)qws;
+  int32_t* finfo = (int32_t*)(w + L.oinfo);
+  double* rel = (double*)(w + L.orel);
+  int32_t* cnt = (int32_t*)(w + L.ocnt);
+  lq_data nd = *d;
+  nd.Q = a.Qn; nd.R = a.Rn; nd.S = a.Sn; nd.q = a.qn; nd.r = a.rn; nd.f = a.fn; nd.x0 = a.x0n;
+  const lq_solve_opts so = {1e-10, 0, 0};
+  const int maxN = p->maxN, nxm = p->maxnx, num = p->maxnu;
+  hipError_t e = lq::qp_launch(0, a, maxN, nxm, num, st, nullptr, nullptr);
+  if (e != hipSuccess) return launch_status(e, fn);
+  for (int outer = 0; outer < o->max_outer; ++outer) {
+    for (int inner = 0; inner < o->max_inner; ++inner) {
+      if ((e = lq::qp_launch(1, a, maxN, nxm, num, st, nullptr, nullptr)) != hipSuccess) return launch_status(e, fn);
+      if ((rc = lq_factor(p, &nd, pws, finfo, st))) return rc;
+      if ((rc = lq_solve(p, &nd, pws, &so, a.dx, a.du, a.dlam, rel, nullptr, finfo, st))) return rc;
+      if ((e = lq::qp_launch(2, a, maxN, nxm, num, st, finfo, cnt)) != hipSuccess) return launch_status(e, fn);
+      int32_t running = 0;
+      if (hipMemcpyAsync(&running, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(LQ_EHIP, "%s: reading the loop count failed", fn);
+      if (running == 0) break;
+    }
+    if ((e = lq::qp_launch(3, a, maxN, nxm, num, st, nullptr, cnt)) != hipSuccess) return launch_status(e, fn);
+    int32_t running = 0;
+    if (hipMemcpyAsync(&running, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(LQ_EHIP, "%s: reading the loop count failed", fn);
+    if (running == 0) break;
+  }
+  return launch_status(lq::qp_finish(a, lam, status, iters, st), fn);
 }
 
 // ---------------------------------------------------------------------------------------------

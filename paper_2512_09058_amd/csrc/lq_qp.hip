@@ -1,0 +1,731 @@
+// Box-constrained LQ QPs: proximal augmented Lagrangian with semismooth Newton inner steps (the
+// paper's Sec. "Solving problems with inequality constraints") and the exact line search of Sec.
+// "Parallel exact line search".  The Newton systems (eq. newton-sys-with-x0 with x_0 eliminated,
+// eq. elim-x0) are written in the layout of the LQ data and solved by lq_factor / lq_solve; the
+// kernels here form them, measure the direction, search the step and update the iterate and the
+// outer variables.  Per instance and stage j the constraint rows are w_j = C_j x_j + D_j u_j with
+// bounds [bl_j, bu_j]; the proximal Sigma-augmented Lagrangian (eq. ocp-al-funcs) at multipliers y
+// and penalties Sigma has the generalised Hessian (eq. qpalm-ocp-hessians)
+//   [[R, S], [S^T, Q]] + [D^T; C^T] Sigma^J [D C] + Gamma^{-1},   J: rows with w + y / Sigma outside
+// [bl, bu], and the gradient [r; q] + H_cost [u; x] + [D^T; C^T] yhat + Gamma^{-1} (z - zbar), with
+// yhat = y + Sigma (w - Pi(w + y / Sigma)).
+#include <float.h>
+#include <math.h>
+
+#include "lq_qp.hpp"
+
+namespace lq {
+
+constexpr int QT = 256;  // threads per workgroup
+constexpr int QSG = 4;   // stages per workgroup in the stage-parallel kernels
+constexpr int NP = 6;    // partial sums per (instance, stage): eta, beta, inner residual, |d|, scale, -
+
+enum { FL_INNER = 0, FL_OUTER = 1, FL_FAIL = 2, FL_ITERS = 3, FL_EXACT = 4, FL_N = 8 };
+
+
+__device__ __forceinline__ double projb(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
+
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < QT / 64; ++i) s += red[i];
+  return s;
+}
+
+__device__ double block_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int i = 1; i < QT / 64; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+__device__ int block_sum_i(int v, int* redi) {
+  const int tid = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((tid & 63) == 0) redi[tid >> 6] = v;
+  __syncthreads();
+  int s = 0;
+  for (int i = 0; i < QT / 64; ++i) s += redi[i];
+  return s;
+}
+
+// x_{k+1} = A_k x_k + B_k u_k + f_k from x_init, the whole workgroup on one instance.
+__device__ void rollout(const QPArgs& a, const Desc& D, double* xs) {
+  const int N = D.N, nx = D.nx, nu = D.nu, tid = threadIdx.x;
+  const double* x0 = a.d.x0 + D.ox0;
+  for (int i = tid; i < nx; i += QT) xs[i] = x0[i];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    const double* Ak = a.d.A + D.oA + (int64_t)k * nx * nx;
+    const double* Bk = a.d.B + D.oB + (int64_t)k * nx * nu;
+    const double* uk = a.u + D.ou + (int64_t)k * nu;
+    double v[1] = {0.0};
+    const int i = tid;
+    if (i < nx) {
+      double s = a.d.f ? a.d.f[D.of + (int64_t)k * nx + i] : 0.0;
+      for (int c = 0; c < nx; ++c) s += Ak[(int64_t)i * nx + c] * xs[c];
+      for (int c = 0; c < nu; ++c) s += Bk[(int64_t)i * nu + c] * uk[c];
+      v[0] = s;
+    }
+    __syncthreads();
+    if (i < nx) {
+      xs[i] = v[0];
+      a.x[D.ox + (int64_t)k * nx + i] = v[0];
+    }
+    __syncthreads();
+  }
+}
+
+// Start: u (0 unless warm), x simulated, y (0 unless warm), penalties, centre, flags, zero parts of
+// the Newton systems.
+__global__ __launch_bounds__(QT) void k_qp_init(QPArgs a) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu, m = a.m;
+  const int64_t R = (int64_t)m * (N + 1), oR = (int64_t)m * D.oK;
+  if (!a.warm) {
+    for (int64_t e = tid; e < (int64_t)N * nu; e += QT) a.u[D.ou + e] = 0.0;
+    for (int64_t e = tid; e < R; e += QT) a.y[oR + e] = 0.0;
+  }
+  for (int64_t e = tid; e < R; e += QT) {
+    a.sig[oR + e] = a.sigma0;
+    a.eprev[oR + e] = INFINITY;
+  }
+  for (int64_t e = tid; e < (int64_t)N * nx; e += QT) a.fn[D.of + e] = 0.0;
+  for (int i = tid; i < nx; i += QT) a.x0n[D.ox0 + i] = 0.0;
+  if (tid < FL_N) a.fl[(int64_t)b * FL_N + tid] = 0;
+  if (tid == 0) a.tau[b] = 0.0;
+  __syncthreads();
+  rollout(a, D, sm);
+  for (int64_t e = tid; e < (int64_t)N * nx; e += QT) a.xbar[D.ox + e] = a.x[D.ox + e];
+  for (int64_t e = tid; e < (int64_t)N * nu; e += QT) a.ubar[D.ou + e] = a.u[D.ou + e];
+}
+
+// Newton system at the iterate, stage by stage (grid: stage groups x instances).
+__global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
+  extern __shared__ double sm[];
+  __shared__ double red[QT / 64];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  if (a.fl[(int64_t)b * FL_N + FL_OUTER]) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu, m = a.m;
+  double* xs = sm;
+  double* us = xs + nx;
+  double* yh = us + nu;
+  double* ss = yh + m;
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
+    const double* xj = j == 0 ? a.d.x0 + D.ox0 : a.x + D.ox + (int64_t)(j - 1) * nx;
+    for (int i = tid; i < nx; i += QT) xs[i] = xj[i];
+    for (int c = tid; c < nu; c += QT) us[c] = j < N ? a.u[D.ou + (int64_t)j * nu + c] : 0.0;
+    __syncthreads();
+    const double* Cj = a.C + (int64_t)m * D.oq + (int64_t)j * m * nx;
+    const double* Dj = j < N ? a.D + (int64_t)m * D.or_ + (int64_t)j * m * nu : nullptr;
+    const int64_t rj = (int64_t)m * D.oK + (int64_t)j * m;
+    double sc = 0.0;
+    for (int i = tid; i < m; i += QT) {
+      double wi = 0.0;
+      for (int c = 0; c < nx; ++c) wi += Cj[(int64_t)i * nx + c] * xs[c];
+      if (Dj)
+        for (int c = 0; c < nu; ++c) wi += Dj[(int64_t)i * nu + c] * us[c];
+      const double s = a.sig[rj + i], yi = a.y[rj + i];
+      const double v = wi + yi / s;
+      const double lo = a.bl[rj + i], hi = a.bu[rj + i];
+      const bool act = v < lo || v > hi;
+      const double h = yi + s * (wi - projb(v, lo, hi));
+      yh[i] = h;
+      ss[i] = act ? s : 0.0;
+      a.w[rj + i] = wi;
+      sc = fmax(sc, fabs(h));
+    }
+    for (int i = tid; i < nx; i += QT) sc = fmax(sc, fabs(xs[i]));
+    for (int c = tid; c < nu; c += QT) sc = fmax(sc, fabs(us[c]));
+    __syncthreads();
+    sc = block_max(sc, red);
+    if (tid == 0) a.part[(D.oK + j) * NP + 4] = sc;
+    // Hessian blocks
+    const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
+    double* Qnj = a.Qn + D.oQ + (int64_t)j * nx * nx;
+    for (int e = tid; e < nx * nx; e += QT) {
+      const int p = e / nx, q = e % nx;
+      double h = 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]) + (p == q ? a.ginv : 0.0);
+      for (int i = 0; i < m; ++i)
+        if (ss[i] != 0.0) h += ss[i] * Cj[(int64_t)i * nx + p] * Cj[(int64_t)i * nx + q];
+      Qnj[e] = h;
+    }
+    const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
+    if (j < N) {
+      const double* Rj = a.d.R + D.oR + (int64_t)j * nu * nu;
+      double* Rnj = a.Rn + D.oR + (int64_t)j * nu * nu;
+      for (int e = tid; e < nu * nu; e += QT) {
+        const int p = e / nu, q = e % nu;
+        double h = 0.5 * (Rj[p * nu + q] + Rj[q * nu + p]) + (p == q ? a.ginv : 0.0);
+        for (int i = 0; i < m; ++i)
+          if (ss[i] != 0.0) h += ss[i] * Dj[(int64_t)i * nu + p] * Dj[(int64_t)i * nu + q];
+        Rnj[e] = h;
+      }
+      double* Snj = a.Sn + D.oS + (int64_t)j * nu * nx;
+      for (int e = tid; e < nu * nx; e += QT) {
+        const int p = e / nx, q = e % nx;
+        double h = Sj ? Sj[e] : 0.0;
+        for (int i = 0; i < m; ++i)
+          if (ss[i] != 0.0) h += ss[i] * Dj[(int64_t)i * nu + p] * Cj[(int64_t)i * nx + q];
+        Snj[e] = h;
+      }
+      // r_j = R_sym u + S x + r + D^T yhat + (u - ubar) / gamma
+      const double* ubj = a.ubar + D.ou + (int64_t)j * nu;
+      for (int c = tid; c < nu; c += QT) {
+        double g = a.d.r[D.or_ + (int64_t)j * nu + c] + a.ginv * (us[c] - ubj[c]);
+        for (int q = 0; q < nu; ++q) g += 0.5 * (Rj[c * nu + q] + Rj[q * nu + c]) * us[q];
+        if (Sj)
+          for (int q = 0; q < nx; ++q) g += Sj[(int64_t)c * nx + q] * xs[q];
+        for (int i = 0; i < m; ++i) g += Dj[(int64_t)i * nu + c] * yh[i];
+        a.rn[D.or_ + (int64_t)j * nu + c] = g;
+      }
+    }
+    // q_j = Q_sym x + q + C^T yhat + S^T u + (x - xbar) / gamma   (stage 0's is not used)
+    const double* xbj = j >= 1 ? a.xbar + D.ox + (int64_t)(j - 1) * nx : nullptr;
+    for (int p = tid; p < nx; p += QT) {
+      double g = a.d.q[D.oq + (int64_t)j * nx + p] + (xbj ? a.ginv * (xs[p] - xbj[p]) : 0.0);
+      for (int q = 0; q < nx; ++q) g += 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]) * xs[q];
+      if (Sj)
+        for (int c = 0; c < nu; ++c) g += Sj[(int64_t)c * nx + p] * us[c];
+      for (int i = 0; i < m; ++i) g += Cj[(int64_t)i * nx + p] * yh[i];
+      a.qn[D.oq + (int64_t)j * nx + p] = g;
+    }
+    __syncthreads();
+  }
+}
+
+// A factorisation that failed ends the instance.
+__global__ void k_qp_check_info(QPArgs a, const int32_t* info) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.batch) return;
+  int32_t* f = a.fl + (int64_t)b * FL_N;
+  if (!f[FL_OUTER] && info[b] != 0) {
+    f[FL_FAIL] = 1;
+    f[FL_OUTER] = 1;
+  }
+}
+
+// Direction measures, stage by stage: G d per row, the stage parts of eta and beta (eq. psi-prime:
+// the cost's quadratic form and gradient along d, with the proximal term), the inner stationarity
+// residual grad + M^T lam with the Newton multipliers, and |d|.
+__global__ __launch_bounds__(QT) void k_qp_dir(QPArgs a) {
+  extern __shared__ double sm[];
+  __shared__ double red[QT / 64];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  if (a.fl[(int64_t)b * FL_N + FL_OUTER] || a.fl[(int64_t)b * FL_N + FL_INNER]) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu, m = a.m;
+  double* xs = sm;
+  double* us = xs + nx;
+  double* dxs = us + nu;
+  double* dus = dxs + nx;
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
+    const double* xj = j == 0 ? a.d.x0 + D.ox0 : a.x + D.ox + (int64_t)(j - 1) * nx;
+    for (int i = tid; i < nx; i += QT) {
+      xs[i] = xj[i];
+      dxs[i] = j == 0 ? 0.0 : a.dx[D.ox + (int64_t)(j - 1) * nx + i];
+    }
+    for (int c = tid; c < nu; c += QT) {
+      us[c] = j < N ? a.u[D.ou + (int64_t)j * nu + c] : 0.0;
+      dus[c] = j < N ? a.du[D.ou + (int64_t)j * nu + c] : 0.0;
+    }
+    __syncthreads();
+    const double* Cj = a.C + (int64_t)m * D.oq + (int64_t)j * m * nx;
+    const double* Dj = j < N ? a.D + (int64_t)m * D.or_ + (int64_t)j * m * nu : nullptr;
+    const int64_t rj = (int64_t)m * D.oK + (int64_t)j * m;
+    double dm = 0.0;
+    for (int i = tid; i < m; i += QT) {
+      double g = 0.0;
+      for (int c = 0; c < nx; ++c) g += Cj[(int64_t)i * nx + c] * dxs[c];
+      if (Dj)
+        for (int c = 0; c < nu; ++c) g += Dj[(int64_t)i * nu + c] * dus[c];
+      a.gd[rj + i] = g;
+    }
+    const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
+    const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
+    const double* xbj = j >= 1 ? a.xbar + D.ox + (int64_t)(j - 1) * nx : nullptr;
+    double eta = 0.0, beta = 0.0, rin = 0.0;
+    if (j >= 1)
+      for (int p = tid; p < nx; p += QT) {
+        double hx = 0.0, gx = a.d.q[D.oq + (int64_t)j * nx + p];
+        for (int q = 0; q < nx; ++q) {
+          const double qs = 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]);
+          hx += qs * dxs[q];
+          gx += qs * xs[q];
+        }
+        if (Sj)
+          for (int c = 0; c < nu; ++c) {
+            hx += Sj[(int64_t)c * nx + p] * dus[c];  // with the u part below: 2 du^T S dx in all
+            gx += Sj[(int64_t)c * nx + p] * us[c];
+          }
+        eta += dxs[p] * hx + a.ginv * dxs[p] * dxs[p];
+        beta += dxs[p] * (gx + a.ginv * (xs[p] - xbj[p]));
+        dm = fmax(dm, fabs(dxs[p]));
+        // inner residual of the x_j row: q_j + A_j^T lam_j - lam_{j-1}
+        double r = a.qn[D.oq + (int64_t)j * nx + p] - a.dlam[D.olam + (int64_t)(j - 1) * nx + p];
+        if (j < N) {
+          const double* Aj = a.d.A + D.oA + (int64_t)j * nx * nx;
+          for (int q = 0; q < nx; ++q) r += Aj[(int64_t)q * nx + p] * a.dlam[D.olam + (int64_t)j * nx + q];
+        }
+        rin = fmax(rin, fabs(r));
+      }
+    if (j < N) {
+      const double* Rj = a.d.R + D.oR + (int64_t)j * nu * nu;
+      const double* Bj = a.d.B + D.oB + (int64_t)j * nx * nu;
+      const double* ubj = a.ubar + D.ou + (int64_t)j * nu;
+      for (int c = tid; c < nu; c += QT) {
+        double hu = 0.0, gu = a.d.r[D.or_ + (int64_t)j * nu + c];
+        for (int q = 0; q < nu; ++q) {
+          const double rs = 0.5 * (Rj[c * nu + q] + Rj[q * nu + c]);
+          hu += rs * dus[q];
+          gu += rs * us[q];
+        }
+        if (Sj)
+          for (int q = 0; q < nx; ++q) {
+            hu += Sj[(int64_t)c * nx + q] * dxs[q];
+            gu += Sj[(int64_t)c * nx + q] * xs[q];
+          }
+        eta += dus[c] * hu + a.ginv * dus[c] * dus[c];
+        beta += dus[c] * (gu + a.ginv * (us[c] - ubj[c]));
+        dm = fmax(dm, fabs(dus[c]));
+        double r = a.rn[D.or_ + (int64_t)j * nu + c];
+        for (int q = 0; q < nx; ++q) r += Bj[(int64_t)q * nu + c] * a.dlam[D.olam + (int64_t)j * nx + q];
+        rin = fmax(rin, fabs(r));
+      }
+    }
+    eta = block_sum(eta, red);
+    beta = block_sum(beta, red);
+    rin = block_max(rin, red);
+    dm = block_max(dm, red);
+    if (tid == 0) {
+      double* pj = a.part + (D.oK + j) * NP;
+      pj[0] = eta;
+      pj[1] = beta;
+      pj[2] = rin;
+      pj[3] = dm;
+    }
+    __syncthreads();
+  }
+}
+
+// psi'(t) = eta t + beta + sum_i delta_i [delta_i t - alpha_i]_+ (eq. psi-prime) over the rows of
+// one instance, each thread taking a contiguous chunk of rows (lower then upper bound of a row).
+struct LineRows {
+  const double *w, *gd, *y, *sig, *bl, *bu;
+  int64_t R, chunk;
+};
+
+__device__ __forceinline__ void row_terms(const LineRows& L, int64_t r, double& d0, double& a0, double& d1,
+                                          double& a1, bool& h0, bool& h1) {
+  const double s = L.sig[r], rs = sqrt(s), g = L.gd[r], w = L.w[r], y = L.y[r];
+  const double lo = L.bl[r], hi = L.bu[r];
+  h0 = lo > -INFINITY;
+  h1 = hi < INFINITY;
+  d0 = -rs * g;
+  a0 = h0 ? (y + s * (w - lo)) / rs : 0.0;
+  d1 = rs * g;
+  a1 = h1 ? -(y + s * (w - hi)) / rs : 0.0;
+}
+
+__device__ double slope_at(const LineRows& L, double eta, double beta, double t, double* red) {
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  const int64_t r0 = tid * L.chunk, r1 = min(L.R, r0 + L.chunk);
+  for (int64_t r = r0; r < r1; ++r) {
+    double d0, a0, d1, a1;
+    bool h0, h1;
+    row_terms(L, r, d0, a0, d1, a1, h0, h1);
+    if (h0) acc += d0 * fmax(d0 * t - a0, 0.0);
+    if (h1) acc += d1 * fmax(d1 * t - a1, 0.0);
+  }
+  return eta * t + beta + block_sum(acc, red);
+}
+
+// Breakpoints t_i = alpha_i / delta_i strictly inside (lo, hi) owned by this thread (count, or the
+// k-th of them in index order).
+__device__ int local_breaks(const LineRows& L, double lo, double hi, int k, double* kth) {
+  const int tid = threadIdx.x;
+  int c = 0;
+  const int64_t r0 = tid * L.chunk, r1 = min(L.R, r0 + L.chunk);
+  for (int64_t r = r0; r < r1; ++r) {
+    double d0, a0, d1, a1;
+    bool h0, h1;
+    row_terms(L, r, d0, a0, d1, a1, h0, h1);
+    if (h0 && d0 != 0.0) {
+      const double t = a0 / d0;
+      if (t > lo && t < hi) {
+        if (c == k) *kth = t;
+        ++c;
+      }
+    }
+    if (h1 && d1 != 0.0) {
+      const double t = a1 / d1;
+      if (t > lo && t < hi) {
+        if (c == k) *kth = t;
+        ++c;
+      }
+    }
+  }
+  return c;
+}
+
+// Exact line search, one workgroup per instance: the inner-loop test first (stationarity residual,
+// a direction at rounding level), then the bisection over the breakpoints of psi' (a breakpoint in
+// the current bracket chosen as pivot: the median in index order; psi' at it decides the side), the
+// root on the last linear piece, and whether a full step crosses no breakpoint (the model is exact
+// there: the inner minimiser).
+__global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
+  __shared__ double red[QT / 64];
+  __shared__ int redi[QT / 64];
+  __shared__ int scnt[QT];
+  __shared__ double s_piv;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  int32_t* f = a.fl + (int64_t)b * FL_N;
+  if (f[FL_OUTER] || f[FL_INNER]) {
+    if (tid == 0) a.tau[b] = 0.0;
+    return;
+  }
+  const Desc D = a.desc[b];
+  const int N = D.N;
+  double eta = 0.0, beta = 0.0, rin = 0.0, dm = 0.0, sc = 1.0;
+  for (int j = tid; j <= N; j += QT) {
+    const double* pj = a.part + (D.oK + j) * NP;
+    eta += pj[0];
+    beta += pj[1];
+    rin = fmax(rin, pj[2]);
+    dm = fmax(dm, pj[3]);
+    sc = fmax(sc, pj[4]);
+  }
+  eta = block_sum(eta, red);
+  beta = block_sum(beta, red);
+  rin = block_max(rin, red);
+  dm = block_max(dm, red);
+  sc = block_max(sc, red);
+  if (rin <= a.inner_tol * sc || dm <= 1e-15 * sc) {
+    if (tid == 0) {
+      a.tau[b] = 0.0;
+      f[FL_INNER] = 1;
+    }
+    return;
+  }
+  LineRows L;
+  const int64_t o = (int64_t)a.m * D.oK;
+  L.w = a.w + o; L.gd = a.gd + o; L.y = a.y + o; L.sig = a.sig + o; L.bl = a.bl + o; L.bu = a.bu + o;
+  L.R = (int64_t)a.m * (N + 1);
+  L.chunk = (L.R + QT - 1) / QT;
+  double tau;
+  const double s0 = slope_at(L, eta, beta, 0.0, red);
+  if (!(s0 < 0.0)) {
+    tau = 1.0;  // the decrease is below the rounding of psi': take the full Newton step
+  } else {
+    double lo = 0.0, hi = INFINITY;
+    bool done = false;
+    tau = 0.0;
+    for (int it = 0; it < 200 && !done; ++it) {
+      double dummy = 0.0;
+      const int c = local_breaks(L, lo, hi, -1, &dummy);
+      scnt[tid] = c;
+      __syncthreads();
+      if (tid == 0) {
+        int acc = 0;
+        for (int i = 0; i < QT; ++i) {
+          const int v = scnt[i];
+          scnt[i] = acc;
+          acc += v;
+        }
+        redi[0] = acc;
+      }
+      __syncthreads();
+      const int total = redi[0];
+      if (total == 0) break;
+      const int rank = total / 2, pre = scnt[tid];
+      if (rank >= pre && rank < pre + c) {
+        double t = 0.0;
+        local_breaks(L, lo, hi, rank - pre, &t);
+        s_piv = t;
+      }
+      __syncthreads();
+      const double tp = s_piv;
+      const double sp = slope_at(L, eta, beta, tp, red);
+      if (sp == 0.0) {
+        tau = tp;
+        done = true;
+      } else if (sp < 0.0) {
+        lo = tp;
+      } else {
+        hi = tp;
+      }
+    }
+    if (!done) {
+      // psi' is linear on (lo, hi): its root from two interior points
+      const double t0 = hi < INFINITY ? lo + 0.25 * (hi - lo) : lo + 1.0;
+      const double t1 = hi < INFINITY ? lo + 0.75 * (hi - lo) : lo + 2.0;
+      const double f0 = slope_at(L, eta, beta, t0, red), f1 = slope_at(L, eta, beta, t1, red);
+      tau = t0 - f0 * (t1 - t0) / (f1 - f0);
+      tau = fmin(fmax(tau, lo), hi);
+    }
+  }
+  // full step with no breakpoint crossed: the model is exact, the step ends the inner loop
+  int exact = 0;
+  if (fabs(tau - 1.0) <= 1e-8) {
+    double dummy = 0.0;
+    const int c = local_breaks(L, 0.0, tau, -1, &dummy);
+    exact = block_sum_i(c, redi) == 0;
+  }
+  if (tid == 0) {
+    a.tau[b] = tau;
+    f[FL_ITERS] += 1;
+    f[FL_EXACT] = exact;
+  }
+}
+
+// z <- z + tau d (grid: stage groups x instances); an exact full step ends the inner loop.
+__global__ __launch_bounds__(QT) void k_qp_step(QPArgs a) {
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const double t = a.tau[b];
+  int32_t* f = a.fl + (int64_t)b * FL_N;
+  if (t == 0.0) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu;
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j < N; ++j) {
+    for (int i = tid; i < nx; i += QT) a.x[D.ox + (int64_t)j * nx + i] += t * a.dx[D.ox + (int64_t)j * nx + i];
+    for (int c = tid; c < nu; c += QT) a.u[D.ou + (int64_t)j * nu + c] += t * a.du[D.ou + (int64_t)j * nu + c];
+  }
+  if (blockIdx.x == 0 && tid == 0 && f[FL_EXACT]) f[FL_INNER] = 1;
+}
+
+// Number of instances still iterating: inner (outer and inner not done) or outer.
+__global__ void k_qp_count(QPArgs a, int which, int32_t* out) {
+  __shared__ int redi[QT / 64];
+  int c = 0;
+  for (int b = threadIdx.x; b < a.batch; b += QT) {
+    const int32_t* f = a.fl + (int64_t)b * FL_N;
+    c += which == 0 ? (!f[FL_OUTER] && !f[FL_INNER]) : !f[FL_OUTER];
+  }
+  c = block_sum_i(c, redi);
+  if (threadIdx.x == 0) *out = c;
+}
+
+// Outer step, rows and stages: yhat, the violation e = (yhat - y) / Sigma, y <- yhat; partial maxima
+// of |e| and |z - zbar| / gamma.
+__global__ __launch_bounds__(QT) void k_qp_outer(QPArgs a) {
+  extern __shared__ double sm[];
+  __shared__ double red[QT / 64];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  if (a.fl[(int64_t)b * FL_N + FL_OUTER]) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu, m = a.m;
+  double* xs = sm;
+  double* us = xs + nx;
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
+    const double* xj = j == 0 ? a.d.x0 + D.ox0 : a.x + D.ox + (int64_t)(j - 1) * nx;
+    for (int i = tid; i < nx; i += QT) xs[i] = xj[i];
+    for (int c = tid; c < nu; c += QT) us[c] = j < N ? a.u[D.ou + (int64_t)j * nu + c] : 0.0;
+    __syncthreads();
+    const double* Cj = a.C + (int64_t)m * D.oq + (int64_t)j * m * nx;
+    const double* Dj = j < N ? a.D + (int64_t)m * D.or_ + (int64_t)j * m * nu : nullptr;
+    const int64_t rj = (int64_t)m * D.oK + (int64_t)j * m;
+    double em = 0.0, dz = 0.0;
+    for (int i = tid; i < m; i += QT) {
+      double wi = 0.0;
+      for (int c = 0; c < nx; ++c) wi += Cj[(int64_t)i * nx + c] * xs[c];
+      if (Dj)
+        for (int c = 0; c < nu; ++c) wi += Dj[(int64_t)i * nu + c] * us[c];
+      const double s = a.sig[rj + i], yi = a.y[rj + i];
+      const double h = yi + s * (wi - projb(wi + yi / s, a.bl[rj + i], a.bu[rj + i]));
+      const double ei = (h - yi) / s;
+      a.e[rj + i] = ei;
+      a.y[rj + i] = h;
+      em = fmax(em, fabs(ei));
+    }
+    if (j >= 1)
+      for (int i = tid; i < nx; i += QT) dz = fmax(dz, fabs(xs[i] - a.xbar[D.ox + (int64_t)(j - 1) * nx + i]));
+    if (j < N)
+      for (int c = tid; c < nu; c += QT) dz = fmax(dz, fabs(us[c] - a.ubar[D.ou + (int64_t)j * nu + c]));
+    em = block_max(em, red);
+    dz = block_max(dz, red);
+    if (tid == 0) {
+      a.part[(D.oK + j) * NP + 0] = em;
+      a.part[(D.oK + j) * NP + 1] = dz * a.ginv;
+    }
+    __syncthreads();
+  }
+}
+
+// Outer decision per instance; a continuing instance gets its states simulated again from u and a
+// new inner loop.
+__global__ __launch_bounds__(QT) void k_qp_outer_fin(QPArgs a) {
+  extern __shared__ double sm[];
+  __shared__ double red[QT / 64];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  int32_t* f = a.fl + (int64_t)b * FL_N;
+  if (f[FL_OUTER]) return;
+  const Desc D = a.desc[b];
+  double em = 0.0, dz = 0.0;
+  for (int j = tid; j <= D.N; j += QT) {
+    em = fmax(em, a.part[(D.oK + j) * NP + 0]);
+    dz = fmax(dz, a.part[(D.oK + j) * NP + 1]);
+  }
+  em = block_max(em, red);
+  dz = block_max(dz, red);
+  if (em <= a.eps && dz <= a.eps) {
+    if (tid == 0) f[FL_OUTER] = 1;
+    return;
+  }
+  rollout(a, D, sm);
+  if (tid == 0) f[FL_INNER] = 0;
+}
+
+// Penalties of rows whose violation did not shrink enough, the previous violation, the new centre.
+__global__ __launch_bounds__(QT) void k_qp_outer_upd(QPArgs a) {
+  const int b = blockIdx.y, tid = threadIdx.x;
+  if (a.fl[(int64_t)b * FL_N + FL_OUTER]) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu, m = a.m;
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
+    const int64_t rj = (int64_t)m * D.oK + (int64_t)j * m;
+    for (int i = tid; i < m; i += QT) {
+      const double ae = fabs(a.e[rj + i]);
+      if (ae > a.theta * a.eprev[rj + i]) a.sig[rj + i] = fmin(a.sigma_max, a.sigma_up * a.sig[rj + i]);
+      a.eprev[rj + i] = ae;
+    }
+    if (j >= 1)
+      for (int i = tid; i < nx; i += QT)
+        a.xbar[D.ox + (int64_t)(j - 1) * nx + i] = a.x[D.ox + (int64_t)(j - 1) * nx + i];
+    if (j < N)
+      for (int c = tid; c < nu; c += QT) a.ubar[D.ou + (int64_t)j * nu + c] = a.u[D.ou + (int64_t)j * nu + c];
+  }
+}
+
+// Status and step counts; the multipliers of the dynamics from the last Newton solve.
+__global__ void k_qp_final(QPArgs a, double* lam, int32_t* status, int32_t* iters) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const Desc D = a.desc[b];
+  const int32_t* f = a.fl + (int64_t)b * FL_N;
+  for (int64_t e = tid; e < (int64_t)D.N * D.nx; e += blockDim.x) lam[D.olam + e] = a.dlam[D.olam + e];
+  if (tid == 0) {
+    status[b] = f[FL_FAIL] ? 2 : (f[FL_OUTER] ? 0 : 1);
+    iters[b] = f[FL_ITERS];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side.
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+QPLayout qp_layout(const int64_t* totals, int64_t sumK, int batch, int m) {
+  // totals: elements of Q, R, S, q, r, f, x0, x, u, lam (plan layout)
+  QPLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = al256(o + bytes);
+    return r;
+  };
+  L.oQn = take(8 * totals[0]);
+  L.oRn = take(8 * totals[1]);
+  L.oSn = take(8 * totals[2]);
+  L.oqn = take(8 * totals[3]);
+  L.orn = take(8 * totals[4]);
+  L.ofn = take(8 * totals[5]);
+  L.ox0n = take(8 * totals[6]);
+  L.odx = take(8 * totals[7]);
+  L.odu = take(8 * totals[8]);
+  L.odlam = take(8 * totals[9]);
+  L.oxb = take(8 * totals[7]);
+  L.oub = take(8 * totals[8]);
+  const size_t rows = 8 * (size_t)m * sumK;
+  L.osig = take(rows);
+  L.ow = take(rows);
+  L.ogd = take(rows);
+  L.oe = take(rows);
+  L.oep = take(rows);
+  L.opart = take(8 * (size_t)NP * sumK);
+  L.otau = take(8 * (size_t)batch);
+  L.ofl = take(4 * (size_t)FL_N * batch);
+  L.orel = take(8 * (size_t)batch);
+  L.oinfo = take(4 * (size_t)batch);
+  L.ocnt = take(4 * 2);
+  L.total = o;
+  return L;
+}
+
+QPArgs qp_args(const Desc* desc, int batch, int m, const lq_data& d, const lq_qp_constraints& c, const lq_qp_opts& op,
+               void* ws, const QPLayout& L, double* x, double* u, double* y) {
+  char* w = (char*)ws;
+  QPArgs a = {};
+  a.desc = desc;
+  a.batch = batch;
+  a.m = m;
+  a.d = d;
+  a.C = c.C; a.D = c.D; a.bl = c.bl; a.bu = c.bu;
+  a.Qn = (double*)(w + L.oQn); a.Rn = (double*)(w + L.oRn); a.Sn = (double*)(w + L.oSn);
+  a.qn = (double*)(w + L.oqn); a.rn = (double*)(w + L.orn); a.fn = (double*)(w + L.ofn); a.x0n = (double*)(w + L.ox0n);
+  a.x = x; a.u = u; a.y = y;
+  a.dx = (double*)(w + L.odx); a.du = (double*)(w + L.odu); a.dlam = (double*)(w + L.odlam);
+  a.xbar = (double*)(w + L.oxb); a.ubar = (double*)(w + L.oub);
+  a.sig = (double*)(w + L.osig); a.w = (double*)(w + L.ow); a.gd = (double*)(w + L.ogd);
+  a.e = (double*)(w + L.oe); a.eprev = (double*)(w + L.oep);
+  a.part = (double*)(w + L.opart); a.tau = (double*)(w + L.otau); a.fl = (int32_t*)(w + L.ofl);
+  a.sigma0 = op.sigma0; a.ginv = 1.0 / op.gamma; a.eps = op.eps; a.theta = op.theta; a.sigma_up = op.sigma_up;
+  a.sigma_max = op.sigma_max; a.inner_tol = op.inner_tol; a.warm = op.warm;
+  return a;
+}
+
+size_t qp_stage_lds(int nxmax, int numax, int m) { return sizeof(double) * (2 * (size_t)nxmax + 2 * numax + 2 * m + 8); }
+
+hipError_t qp_launch(int which, const QPArgs& a, int maxN, int nxmax, int numax, hipStream_t st, const int32_t* info,
+                     int32_t* out) {
+  const size_t lds = qp_stage_lds(nxmax, numax, a.m);
+  const dim3 sgrid((maxN + 1 + QSG - 1) / QSG, a.batch);
+  hipError_t e;
+  switch (which) {
+    case 0:
+      if ((e = raise_lds_limit((const void*)k_qp_init, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_init, dim3(a.batch), dim3(QT), lds, st, a);
+      break;
+    case 1:
+      if ((e = raise_lds_limit((const void*)k_qp_newton, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_newton, sgrid, dim3(QT), lds, st, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_qp_check_info, dim3((a.batch + 255) / 256), dim3(256), 0, st, a, info);
+      if ((e = raise_lds_limit((const void*)k_qp_dir, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_dir, sgrid, dim3(QT), lds, st, a);
+      hipLaunchKernelGGL(k_qp_search, dim3(a.batch), dim3(QT), 0, st, a);
+      hipLaunchKernelGGL(k_qp_step, sgrid, dim3(QT), 0, st, a);
+      hipLaunchKernelGGL(k_qp_count, dim3(1), dim3(QT), 0, st, a, 0, out);
+      break;
+    case 3:
+      if ((e = raise_lds_limit((const void*)k_qp_outer, lds)) != hipSuccess) return e;
+      if ((e = raise_lds_limit((const void*)k_qp_outer_fin, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_outer, sgrid, dim3(QT), lds, st, a);
+      hipLaunchKernelGGL(k_qp_outer_fin, dim3(a.batch), dim3(QT), lds, st, a);
+      hipLaunchKernelGGL(k_qp_outer_upd, sgrid, dim3(QT), 0, st, a);
+      hipLaunchKernelGGL(k_qp_count, dim3(1), dim3(QT), 0, st, a, 1, out);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t qp_finish(const QPArgs& a, double* lam, int32_t* status, int32_t* iters, hipStream_t st) {
+  hipLaunchKernelGGL(k_qp_final, dim3(a.batch), dim3(QT), 0, st, a, lam, status, iters);
+  return hipGetLastError();
+}
+
+}  // namespace lq

@@ -910,6 +910,107 @@ def bench_update(args):
     print(json.dumps(out))
 
 
+def bench_qp(args):
+    """Box-constrained QPs of the paper's mass-spring benchmark (M = 12 masses: nx = 24, nu = 6,
+    m = 30 bound rows per stage, N = 128, 150 initial states), solved by the proximal augmented
+    Lagrangian / semismooth Newton path with its Newton systems on the library's factor and solve:
+    cold start (zeros), then, as in the paper's warm-start experiment, the next MPC problem (the first
+    input applied to each instance) started from the previous solution shifted by one stage."""
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    from paper_2512_09058_amd import qp as Q
+    from oracle import qp as oqp
+    M, N, count = 12, 128, 150
+    P = args.qp_intervals
+    prob, C, D, bl, bu = synth.mass_spring(M, N, count, seed=0)
+    nx, nu = prob.nx, prob.nu
+    plan = L.Plan(N, nx, nu, batch=count, mode="f64")
+    data = L.pack(prob)
+    cons = Q.pack_constraints([C] * count, [D] * count, [bl] * count, [bu] * count)
+    m = cons["m"]
+    ws, qws = plan.workspace(), Q.workspace(plan, m, P)
+    x, u, lam = plan.empty_outputs()
+    y = torch.zeros(count * (N + 1) * m, dtype=torch.float64, device="cuda")
+    status = torch.zeros(count, dtype=torch.int32, device="cuda")
+    iters = torch.zeros(count, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(d, warm, u0=None, y0=None):
+        ts = []
+        for s_ in range(args.warmup + args.steps):
+            if warm:
+                u.copy_(u0)
+                y.copy_(y0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            Q.solve(plan, d, cons, ws, qws, x, u, lam, y, status, iters, opts={"warm": int(warm), "intervals": P},
+                    stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if s_ >= args.warmup:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.mean(ts)), float(np.max(ts))
+
+    cold_ms, cold_max = timed(data, False)
+    st_cold, it_cold = status.cpu().numpy(), iters.cpu().numpy()
+    uh = u.view(count, N, nu).cpu().numpy()
+    yh = y.view(count, N + 1, m).cpu().numpy()
+    sol0 = [L.unpack(plan, n_, t_, 0) for n_, t_ in (("x", x), ("u", u), ("lam", lam))]
+    # the next MPC problem: x_init <- A x_init + B u_0; start from the solution shifted by one stage
+    x1 = np.einsum("bij,bj->bi", prob.A[:, 0], prob.x0) + np.einsum("bij,bj->bi", prob.B[:, 0], uh[:, 0])
+    data2 = dict(data)
+    data2["x0"] = torch.from_numpy(np.ascontiguousarray(x1).reshape(-1)).to("cuda")
+    us = np.concatenate([uh[:, 1:], uh[:, -1:]], axis=1)
+    ys = np.concatenate([yh[:, 1:], yh[:, -1:]], axis=1)
+    warm_ms, warm_max = timed(data2, True, torch.from_numpy(us.reshape(-1)).to("cuda"),
+                              torch.from_numpy(ys.reshape(-1)).to("cuda"))
+    st_warm, it_warm = status.cpu().numpy(), iters.cpu().numpy()
+    # checks: the oracle's certificate of sampled GPU results and its solution of instance 0 (cold)
+    cert = []
+    for i in (0, count - 1):
+        p2 = prob.instance(i)
+        p2.x0 = x1[i]
+        xs, uu, ls = (L.unpack(plan, n_, t_, i) for n_, t_ in (("x", x), ("u", u), ("lam", lam)))
+        cert.append(max(oqp.certificate(p2, C, D, bl, bu, xs, uu, ls, y.view(count, N + 1, m)[i].cpu().numpy())))
+    cpu = None
+    fwd = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        cnt = 0
+        while time.perf_counter() - t0 < 10.0 and cnt < count:
+            r = oqp.solve(prob.instance(cnt), C, D, bl, bu, linear="banded")
+            if cnt == 0:
+                fwd = max(np.abs(a - b).max() for a, b in zip(sol0, r[:3])) / max(np.abs(b).max() for b in r[:3])
+            cnt += 1
+        tc = (time.perf_counter() - t0) / cnt
+        cpu = {"value": 1.0 / tc, "unit": "QPs/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{cnt} cold-start instances through the oracle's augmented-Lagrangian solver with banded "
+                         f"Newton solves (numpy float64, one process), {tc:.2f} s per QP",
+               "gpu_vs_oracle_inst0_fwd_err": fwd}
+    out = {"metric": "box-constrained QP solves/s, mass-spring benchmark M=12 (nx=24, nu=6), N=128, 150 initial states",
+           "value": count / (cold_ms * 1e-3), "unit": "QPs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": cold_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (the paper's mass-spring problem generated from its equations; seeded initial states)",
+           "config": {"workload": "mass-spring M=12, N=128, 150 QPs, box bounds |pos| <= 4, |u| <= 0.5",
+                      "batch": count, "N": N, "nx": nx, "nu": nu, "m": m,
+                      "newton_systems": f"parallel-in-time, {P} intervals" if P > 1 else "serial plan"},
+           "cold": {"ms_batch": cold_ms, "ms_batch_max": cold_max, "converged": int((st_cold == 0).sum()),
+                    "inner_steps_mean": float(it_cold.mean()), "inner_steps_max": int(it_cold.max())},
+           "warm": {"ms_batch": warm_ms, "ms_batch_max": warm_max, "converged": int((st_warm == 0).sum()),
+                    "inner_steps_mean": float(it_warm.mean()), "inner_steps_max": int(it_warm.max()),
+                    "qps_per_s": count / (warm_ms * 1e-3)},
+           "certificate_max_sampled": max(cert),
+           "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": "ms", "frac": None,
+                        "traffic": None,
+                        "note": "a chain of dependent Newton steps (factor, solve, line search) with one host "
+                                "synchronisation per step; per-kernel times in the kernel trace"},
+           "cpu_baseline": cpu}
+    print(f"[bench] qp: cold {cold_ms:.2f} ms ({it_cold.mean():.1f} steps), warm {warm_ms:.2f} ms "
+          f"({it_warm.mean():.1f} steps)", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -921,10 +1022,12 @@ def main():
     ap.add_argument("--distinct", type=int, default=0,
                     help="large / adjoint workloads: generate only this many distinct instances and repeat them "
                          "(0: all distinct)")
+    ap.add_argument("--qp-intervals", type=int, default=0,
+                    help="QP workload: intervals of the parallel-in-time Newton solves (0: serial plan)")
     ap.add_argument("--pit-intervals", type=int, nargs="*", default=[4, 8, 16],
                     help="large workload: interval counts of the parallel-in-time path")
     ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20", "blocktri",
-                                           "update4096", "update1024x60"],
+                                           "update4096", "update1024x60", "qp_mass_spring"],
                     default="batch4096",
                     help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
                          "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")
@@ -966,6 +1069,8 @@ def main():
         return bench_blocktri(args)
     if args.workload in UPDATE_SHAPES:
         return bench_update(args)
+    if args.workload == "qp_mass_spring":
+        return bench_qp(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)

@@ -19,19 +19,21 @@
  *   start: u = 0 (or the given u when warm), x simulated from x_init, y = 0 (or the given y),
  *   Sigma = sigma0, Gamma = gamma I, proximal centre = the start;
  *   inner: generalised Hessian and gradient of the augmented Lagrangian at the iterate (active rows
- *   (Cx + Du + y / Sigma) outside [bl, bu]), Newton direction by lq_factor + lq_solve (the iterate
- *   satisfies the dynamics, so the direction's dynamics residual is 0), exact step along it; the
+ *   (Cx + Du + y / Sigma) outside [bl, bu]), Newton direction by lq_factor + lq_solve, or with
+ *   intervals > 1 by the parallel-in-time lq_pit_factor + lq_pit_solve (the iterate satisfies the
+ *   dynamics, so the direction's dynamics residual is 0), exact step along it; the
  *   inner loop of an instance ends when its inner stationarity residual ||grad + M^T lam||_inf is at
  *   most inner_tol max(1, ||z||_inf, ||yhat||_inf), when a full step changes no row's activity, or
- *   after max_inner steps; a step is x <- x + tau dx, u <- u + tau du, and x is simulated again from
- *   u at every outer iteration;
+ *   after max_inner steps; a step is u <- u + tau du with x simulated again from u (x + tau dx in exact
+ *   arithmetic; the dynamics stay exact whatever the accuracy of the Newton solve);
  *   outer: y <- yhat, stop when ||Cx + Du - Pi(Cx + Du + y / Sigma)||_inf <= eps and
  *   ||z - zbar||_inf / gamma <= eps, else Sigma_i <- min(sigma_max, sigma_up Sigma_i) on rows whose
  *   violation did not fall below theta times the previous one, centre <- z.
  * Outputs: x, u (the QP solution), lam (multipliers of the dynamics), y (of the bounds: positive at
  * an active upper bound, negative at a lower one), status[batch] (0 converged, 1 max_outer reached,
  * 2 a Newton factorisation failed), iters[batch] (inner steps taken).
- * Requirements: a float64 plan without checkpoints; m <= 256.  The call synchronises with the host
+ * Requirements: a float64 plan without checkpoints; m <= 256; intervals > 1 needs a uniform plan
+ * and 1 < intervals <= N.  The call synchronises with the host
  * once per inner step (the loops end when every instance is done).
  */
 #ifndef LQQP_H
@@ -67,15 +69,17 @@ typedef struct {
   int32_t max_outer; /* e.g. 100 */
   int32_t max_inner; /* per outer iteration, e.g. 50 */
   int32_t warm;      /* 1: start from the u and y passed in */
-  int32_t pad;
+  int32_t intervals; /* 0 or 1: Newton systems by lq_factor / lq_solve; P > 1: by the parallel-in-time
+                        lq_pit_factor / lq_pit_solve with P intervals (uniform plans; lqpit.h) */
 } lq_qp_opts;
 
 /* Bytes of the QP workspace (the Newton systems' data, the direction, the rows' state, partial
- * sums, per-instance flags; 256-byte aligned, caller-owned) for this plan and m rows per stage. */
-size_t lq_qp_workspace_bytes(const lq_plan* plan, int32_t m);
+ * sums, per-instance flags, and with intervals > 1 the parallel-in-time factors; 256-byte aligned,
+ * caller-owned) for this plan, m rows per stage and the number of intervals (0 or 1: serial). */
+size_t lq_qp_workspace_bytes(const lq_plan* plan, int32_t m, int32_t intervals);
 
 /* Solves every instance's QP.  plan_workspace: lq_plan_workspace_bytes(plan) bytes (the Newton
- * factors); qp_workspace: lq_qp_workspace_bytes(plan, m) bytes.  Returns LQ_OK / LQ_EINVAL /
+ * factors of the serial path); qp_workspace: lq_qp_workspace_bytes(plan, m, opts->intervals) bytes.  Returns LQ_OK / LQ_EINVAL /
  * LQ_EUNSUPPORTED / LQ_EHIP; per-instance outcomes in status and iters (device int32[batch]). */
 int lq_qp_solve(const lq_plan* plan, const lq_data* data, const lq_qp_constraints* cons, const lq_qp_opts* opts,
                 void* plan_workspace, void* qp_workspace, double* x, double* u, double* lam, double* y,

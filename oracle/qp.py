@@ -213,9 +213,10 @@ def rollout(prob, u):
 
 
 def solve(prob, C, D, bl, bu, sigma0=1e2, gamma=1e7, eps=1e-9, theta=0.25, sigma_up=10.0, sigma_max=1e9,
-          max_outer=100, max_inner=50, inner_tol=1e-11, u0=None, y0=None):
+          max_outer=100, max_inner=50, inner_tol=1e-11, u0=None, y0=None, linear="dense"):
     """Proximal ALM with semismooth Newton inner solves.  Returns (x, u, lam, y, stats).
 
+    The Newton systems are solved by ``kkt.solve_dense`` (linear="dense") or ``kkt.solve_banded``.
     Start: u = u0 (0), x by the dynamics; after every step x is simulated again from the new u (the
     same point in exact arithmetic; the dynamics stay exact, which the line search assumes),
     y = y0 (0), Sigma = sigma0, Gamma = gamma I, proximal centre = the start.  Inner loop: Newton
@@ -244,7 +245,7 @@ def solve(prob, C, D, bl, bu, sigma0=1e2, gamma=1e7, eps=1e-9, theta=0.25, sigma
         for inner in range(max_inner):
             stats["inner"] += 1
             npb, yhat, act = newton_problem(prob, C, D, bl, bu, y, sigma, ginv, xbar, ubar, x, u)
-            dx, du, lam = kkt.solve_dense(npb)
+            dx, du, lam = kkt.solve_dense(npb) if linear == "dense" else kkt.solve_banded(npb)
             scale = max(1.0, np.abs(x).max(), np.abs(u).max(), np.abs(yhat).max())
             if inner_residual(prob, npb, lam) <= inner_tol * scale:
                 break                      # inner minimiser to tolerance: no step

@@ -60,7 +60,7 @@ EXPORTS = {
     "lq_update_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "lq_factor_update": (C.c_int, [C.c_void_p, C.POINTER(LqData)] + [C.c_void_p] * 5),
     # box-constrained QPs (include/lqqp.h)
-    "lq_qp_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32]),
+    "lq_qp_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
     "lq_qp_solve": (C.c_int, [C.c_void_p, C.POINTER(LqData)] + [C.c_void_p] * 10 + [C.c_void_p]),
     # parallel-in-time solve (include/lqpit.h)
     "lq_pit_workspace_bytes": (C.c_size_t, [C.c_int32] * 5),

@@ -13,6 +13,7 @@
 
 #include "lq_internal.hpp"
 #include "lq_qp.hpp"
+#include "lqpit.h"
 #include "lqupdate.h"
 
 namespace lq {
@@ -835,11 +836,20 @@ static void qp_totals(const lq_plan* p, int64_t* tot, int64_t* sumK) {
   *sumK = k;
 }
 
-extern "C" size_t lq_qp_workspace_bytes(const lq_plan* p, int32_t m) {
+// The parallel-in-time factors follow the QP workspace's own regions.
+static size_t qp_pit_bytes(const lq_plan* p, int32_t P) {
+  if (P <= 1) return 0;
+  if (!p->uniform) return (size_t)-1;
+  return lq_pit_workspace_bytes(p->batch, p->N[0], p->nx[0], p->nu[0], P);
+}
+
+extern "C" size_t lq_qp_workspace_bytes(const lq_plan* p, int32_t m, int32_t intervals) {
   if (!p || m <= 0) return 0;
   int64_t tot[10], sumK;
   qp_totals(p, tot, &sumK);
-  return lq::qp_layout(tot, sumK, p->batch, m).total;
+  const size_t pit = qp_pit_bytes(p, intervals);
+  if (pit == (size_t)-1 || (intervals > 1 && pit == 0)) return 0;
+  return lq::qp_layout(tot, sumK, p->batch, m).total + pit;
 }
 
 extern "C" int lq_qp_solve(const lq_plan* p, const lq_data* d, const lq_qp_constraints* c, const lq_qp_opts* o,
@@ -858,6 +868,9 @@ extern "C" int lq_qp_solve(const lq_plan* p, const lq_data* d, const lq_qp_const
   if (p->maxnx > 256) return fail(LQ_EUNSUPPORTED, "%s: nx <= 256", fn);
   if (!(o->sigma0 > 0) || !(o->gamma > 0) || !(o->eps > 0) || o->max_outer <= 0 || o->max_inner <= 0)
     return fail(LQ_EINVAL, "%s: sigma0, gamma, eps, max_outer, max_inner must be positive", fn);
+  const int P = o->intervals;
+  if (P > 1 && (!p->uniform || P > p->N[0]))
+    return fail(LQ_EUNSUPPORTED, "%s: intervals > 1 needs a uniform plan and intervals <= N", fn);
   int64_t tot[10], sumK;
   qp_totals(p, tot, &sumK);
   const lq::QPLayout L = lq::qp_layout(tot, sumK, p->batch, c->m);
@@ -875,8 +888,15 @@ extern "C" int lq_qp_solve(const lq_plan* p, const lq_data* d, const lq_qp_const
   for (int outer = 0; outer < o->max_outer; ++outer) {
     for (int inner = 0; inner < o->max_inner; ++inner) {
       if ((e = lq::qp_launch(1, a, maxN, nxm, num, st, nullptr, nullptr)) != hipSuccess) return launch_status(e, fn);
-      if ((rc = lq_factor(p, &nd, pws, finfo, st))) return rc;
-      if ((rc = lq_solve(p, &nd, pws, &so, a.dx, a.du, a.dlam, rel, nullptr, finfo, st))) return rc;
+      if (P > 1) {
+        const int n0 = p->N[0], x0 = p->nx[0], u0 = p->nu[0];
+        void* pitws = w + L.total;
+        if ((rc = lq_pit_factor(p->batch, n0, x0, u0, P, &nd, pitws, finfo, st))) return rc;
+        if ((rc = lq_pit_solve(p->batch, n0, x0, u0, P, &nd, pitws, a.dx, a.du, a.dlam, rel, finfo, st))) return rc;
+      } else {
+        if ((rc = lq_factor(p, &nd, pws, finfo, st))) return rc;
+        if ((rc = lq_solve(p, &nd, pws, &so, a.dx, a.du, a.dlam, rel, nullptr, finfo, st))) return rc;
+      }
       if ((e = lq::qp_launch(2, a, maxN, nxm, num, st, finfo, cnt)) != hipSuccess) return launch_status(e, fn);
       int32_t running = 0;
       if (hipMemcpyAsync(&running, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -491,19 +491,27 @@ __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
   }
 }
 
-// z <- z + tau d (grid: stage groups x instances); an exact full step ends the inner loop.
+// u <- u + tau du (grid: stage groups x instances); an exact full step ends the inner loop.
 __global__ __launch_bounds__(QT) void k_qp_step(QPArgs a) {
   const int b = blockIdx.y, tid = threadIdx.x;
   const double t = a.tau[b];
   int32_t* f = a.fl + (int64_t)b * FL_N;
   if (t == 0.0) return;
   const Desc D = a.desc[b];
-  const int N = D.N, nx = D.nx, nu = D.nu;
-  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j < N; ++j) {
-    for (int i = tid; i < nx; i += QT) a.x[D.ox + (int64_t)j * nx + i] += t * a.dx[D.ox + (int64_t)j * nx + i];
+  const int N = D.N, nu = D.nu;
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j < N; ++j)
     for (int c = tid; c < nu; c += QT) a.u[D.ou + (int64_t)j * nu + c] += t * a.du[D.ou + (int64_t)j * nu + c];
-  }
   if (blockIdx.x == 0 && tid == 0 && f[FL_EXACT]) f[FL_INNER] = 1;
+}
+
+// x simulated from the new u (x + tau dx in exact arithmetic): the iterate keeps the dynamics
+// exactly, which the line search assumes, whatever the accuracy of the Newton solve.
+__global__ __launch_bounds__(QT) void k_qp_rollout(QPArgs a) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x;
+  if (a.tau[b] == 0.0) return;
+  const Desc D = a.desc[b];
+  rollout(a, D, sm);
 }
 
 // Number of instances still iterating: inner (outer and inner not done) or outer.
@@ -707,6 +715,8 @@ hipError_t qp_launch(int which, const QPArgs& a, int maxN, int nxmax, int numax,
       hipLaunchKernelGGL(k_qp_dir, sgrid, dim3(QT), lds, st, a);
       hipLaunchKernelGGL(k_qp_search, dim3(a.batch), dim3(QT), 0, st, a);
       hipLaunchKernelGGL(k_qp_step, sgrid, dim3(QT), 0, st, a);
+      if ((e = raise_lds_limit((const void*)k_qp_rollout, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_rollout, dim3(a.batch), dim3(QT), lds, st, a);
       hipLaunchKernelGGL(k_qp_count, dim3(1), dim3(QT), 0, st, a, 0, out);
       break;
     case 3:

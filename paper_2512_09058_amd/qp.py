@@ -21,11 +21,11 @@ class LqQpConstraints(C.Structure):
 class LqQpOpts(C.Structure):
     _fields_ = [("sigma0", C.c_double), ("gamma", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
                 ("sigma_up", C.c_double), ("sigma_max", C.c_double), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("warm", C.c_int32), ("pad", C.c_int32)]
+                ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("warm", C.c_int32), ("intervals", C.c_int32)]
 
 
 DEFAULTS = dict(sigma0=1e2, gamma=1e7, eps=1e-9, theta=0.25, sigma_up=10.0, sigma_max=1e9, inner_tol=1e-11,
-                max_outer=100, max_inner=50, warm=0)
+                max_outer=100, max_inner=50, warm=0, intervals=0)
 
 
 def pack_constraints(Cs: Sequence[np.ndarray], Ds: Sequence[np.ndarray], bls: Sequence[np.ndarray],
@@ -40,8 +40,8 @@ def pack_constraints(Cs: Sequence[np.ndarray], Ds: Sequence[np.ndarray], bls: Se
     return {"m": m.pop(), "C": flat(Cs), "D": flat(Ds), "bl": flat(bls), "bu": flat(bus)}
 
 
-def workspace(plan: Plan, m: int, device="cuda") -> torch.Tensor:
-    n = int(_lib.load().lq_qp_workspace_bytes(plan.handle, int(m)))
+def workspace(plan: Plan, m: int, intervals: int = 0, device="cuda") -> torch.Tensor:
+    n = int(_lib.load().lq_qp_workspace_bytes(plan.handle, int(m), int(intervals)))
     if n == 0:
         raise ValueError("invalid plan or m")
     return torch.empty(n, dtype=torch.uint8, device=device)
@@ -55,7 +55,7 @@ def solve(plan: Plan, data: Dict[str, torch.Tensor], cons: Dict[str, torch.Tenso
     o.update(opts or {})
     oo = LqQpOpts(float(o["sigma0"]), float(o["gamma"]), float(o["eps"]), float(o["theta"]), float(o["sigma_up"]),
                   float(o["sigma_max"]), float(o["inner_tol"]), int(o["max_outer"]), int(o["max_inner"]),
-                  int(o["warm"]), 0)
+                  int(o["warm"]), int(o["intervals"]))
     cc = LqQpConstraints(int(cons["m"]), _ptr(cons["C"]), _ptr(cons["D"]), _ptr(cons["bl"]), _ptr(cons["bu"]))
     dd = _data(data)
     check(_lib.load().lq_qp_solve(plan.handle, C.byref(dd), C.byref(cc), C.byref(oo), _ptr(ws), _ptr(qws), _ptr(x),

@@ -33,7 +33,7 @@ def _run(insts, Cs, Ds, bls, bus, opts=None, warm=None):
             data[k] = torch.zeros(plan.totals[k], dtype=torch.float64, device="cuda")
     cons = Q.pack_constraints(Cs, Ds, bls, bus)
     ws = plan.workspace()
-    qws = Q.workspace(plan, cons["m"])
+    qws = Q.workspace(plan, cons["m"], (opts or {}).get("intervals", 0))
     x, u, lam = plan.empty_outputs()
     m = cons["m"]
     y = torch.zeros(sum((p.N + 1) * m for p in insts), dtype=torch.float64, device="cuda")
@@ -69,12 +69,12 @@ def _check(insts, Cs, Ds, bls, bus, res, label):
     return iters
 
 
-@pytest.mark.parametrize("M,N", [(6, 8), (6, 16), (12, 8)])
-def test_mass_spring_matches_oracle(M, N):
-    print(f"case: mass-spring M={M} N={N}", flush=True)
+@pytest.mark.parametrize("M,N,P", [(6, 8, 0), (6, 16, 0), (12, 8, 0), (6, 16, 4), (12, 12, 3)])
+def test_mass_spring_matches_oracle(M, N, P):
+    print(f"case: mass-spring M={M} N={N} intervals={P}", flush=True)
     prob, C, D, bl, bu = synth.mass_spring(M, N, 3, seed=5)
     insts = [prob.instance(i) for i in range(3)]
-    res = _run(insts, [C] * 3, [D] * 3, [bl] * 3, [bu] * 3)
+    res = _run(insts, [C] * 3, [D] * 3, [bl] * 3, [bu] * 3, opts={"intervals": P})
     iters = _check(insts, [C] * 3, [D] * 3, [bl] * 3, [bu] * 3, res, "mass-spring")
     print(f"  inner steps {iters.tolist()}", flush=True)
 
@@ -122,3 +122,6 @@ def test_refusals():
     with pytest.raises(RuntimeError, match="positive"):
         Q.solve(plan, data, cons, plan.workspace(), Q.workspace(plan, cons["m"]), x, u, lam, y, st, it,
                 opts={"max_outer": 0})
+    with pytest.raises(RuntimeError, match="intervals"):
+        Q.solve(plan, data, cons, plan.workspace(), Q.workspace(plan, cons["m"], 4), x, u, lam, y, st, it,
+                opts={"intervals": 5})

@@ -227,3 +227,12 @@ def test_planted_mistakes():
     assert abs(qp.merit_slope(eta, beta, bad_delta, alpha, t) - num) > 1e-4
     assert abs(qp.merit_slope(eta, beta + ginv, delta, alpha, t) - num) > 1e-4   # a stray proximal term
     assert abs(qp.merit_slope(eta, beta, delta, alpha, t) - num) < 1e-5
+
+
+def test_banded_newton_solves_match_dense():
+    prob, C, D, bl, bu = synth.mass_spring(6, 6, 1, seed=4)
+    p = prob.instance(0)
+    a = qp.solve(p, C, D, bl, bu)
+    b = qp.solve(p, C, D, bl, bu, linear="banded")
+    for u, v in zip(a[:4], b[:4]):
+        assert np.abs(u - v).max() <= 1e-8 * max(1.0, np.abs(v).max())

@@ -123,6 +123,8 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
   double* us = xs + nx;
   double* yh = us + nu;
   double* ss = yh + m;
+  __shared__ int s_act[256];  // active rows of the stage (the only ones with Sigma^J and yhat nonzero)
+  __shared__ int s_na;
   for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
     const double* xj = j == 0 ? a.d.x0 + D.ox0 : a.x + D.ox + (int64_t)(j - 1) * nx;
     for (int i = tid; i < nx; i += QT) xs[i] = xj[i];
@@ -151,15 +153,25 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
     for (int c = tid; c < nu; c += QT) sc = fmax(sc, fabs(us[c]));
     __syncthreads();
     sc = block_max(sc, red);
-    if (tid == 0) a.part[(D.oK + j) * NP + 4] = sc;
+    if (tid == 0) {
+      a.part[(D.oK + j) * NP + 4] = sc;
+      int na = 0;
+      for (int i = 0; i < m; ++i)
+        if (ss[i] != 0.0) s_act[na++] = i;
+      s_na = na;
+    }
+    __syncthreads();
+    const int na = s_na;
     // Hessian blocks
     const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
     double* Qnj = a.Qn + D.oQ + (int64_t)j * nx * nx;
     for (int e = tid; e < nx * nx; e += QT) {
       const int p = e / nx, q = e % nx;
       double h = 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]) + (p == q ? a.ginv : 0.0);
-      for (int i = 0; i < m; ++i)
-        if (ss[i] != 0.0) h += ss[i] * Cj[(int64_t)i * nx + p] * Cj[(int64_t)i * nx + q];
+      for (int t = 0; t < na; ++t) {
+        const int i = s_act[t];
+        h += ss[i] * Cj[(int64_t)i * nx + p] * Cj[(int64_t)i * nx + q];
+      }
       Qnj[e] = h;
     }
     const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
@@ -169,16 +181,20 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
       for (int e = tid; e < nu * nu; e += QT) {
         const int p = e / nu, q = e % nu;
         double h = 0.5 * (Rj[p * nu + q] + Rj[q * nu + p]) + (p == q ? a.ginv : 0.0);
-        for (int i = 0; i < m; ++i)
-          if (ss[i] != 0.0) h += ss[i] * Dj[(int64_t)i * nu + p] * Dj[(int64_t)i * nu + q];
+        for (int t = 0; t < na; ++t) {
+          const int i = s_act[t];
+          h += ss[i] * Dj[(int64_t)i * nu + p] * Dj[(int64_t)i * nu + q];
+        }
         Rnj[e] = h;
       }
       double* Snj = a.Sn + D.oS + (int64_t)j * nu * nx;
       for (int e = tid; e < nu * nx; e += QT) {
         const int p = e / nx, q = e % nx;
         double h = Sj ? Sj[e] : 0.0;
-        for (int i = 0; i < m; ++i)
-          if (ss[i] != 0.0) h += ss[i] * Dj[(int64_t)i * nu + p] * Cj[(int64_t)i * nx + q];
+        for (int t = 0; t < na; ++t) {
+          const int i = s_act[t];
+          h += ss[i] * Dj[(int64_t)i * nu + p] * Cj[(int64_t)i * nx + q];
+        }
         Snj[e] = h;
       }
       // r_j = R_sym u + S x + r + D^T yhat + (u - ubar) / gamma
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
         for (int q = 0; q < nu; ++q) g += 0.5 * (Rj[c * nu + q] + Rj[q * nu + c]) * us[q];
         if (Sj)
           for (int q = 0; q < nx; ++q) g += Sj[(int64_t)c * nx + q] * xs[q];
-        for (int i = 0; i < m; ++i) g += Dj[(int64_t)i * nu + c] * yh[i];
+        for (int t = 0; t < na; ++t) g += Dj[(int64_t)s_act[t] * nu + c] * yh[s_act[t]];
         a.rn[D.or_ + (int64_t)j * nu + c] = g;
       }
     }
@@ -199,7 +215,7 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
       for (int q = 0; q < nx; ++q) g += 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]) * xs[q];
       if (Sj)
         for (int c = 0; c < nu; ++c) g += Sj[(int64_t)c * nx + p] * us[c];
-      for (int i = 0; i < m; ++i) g += Cj[(int64_t)i * nx + p] * yh[i];
+      for (int t = 0; t < na; ++t) g += Cj[(int64_t)s_act[t] * nx + p] * yh[s_act[t]];
       a.qn[D.oq + (int64_t)j * nx + p] = g;
     }
     __syncthreads();

@@ -46,14 +46,6 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ double rsqrt_f64(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-  const double h = 0.5 * a;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
-}
-
 // Broadcast lane k of each 16-lane row to the whole row (k a constant after unrolling).
 __device__ __forceinline__ double bc(double v, int k) {
   long x = __double_as_longlong(v);
@@ -161,21 +153,50 @@ __device__ __forceinline__ typename MM<TP>::V tmm(typename MM<TP>::V acc, const 
 
 // Right-looking Cholesky of a 16x16 tile held one row per lane (lane c of each 16-lane row:
 // row c in h).  Returns 0, or for the first failing pivot 1 (finite, not positive) or 2 (not
-// finite); failed pivots are replaced by 1, so later pivots of a failed tile are meaningless.  On return h[0..c] is row c of L and dinv = 1 / L[c][c].
-__device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c) {
+// finite); failed pivots are replaced by 1, so later pivots of a failed tile are meaningless.  On
+// return h[0..c] is row c of L and dinv = 1 / L[c][c].
+// Only the first n (wave-uniform) pivots are real: rows and columns n..15 are the identity
+// padding with zero coupling, whose factor is the identity.  The pivots run in chunks of four,
+// each chunk under a uniform branch, and the chunks past the last real pivot are skipped (within
+// a chunk a padding pivot changes nothing but its own diagonal, which stays 1 to rounding).
+// Each pivot updates the next pivot's column first and starts its 1/sqrt before its other
+// trailing updates, so the next pivot's chain overlaps them.
+// 1 / sqrt(d): the hardware estimate y (about 5e-8 relative) with one third-order correction,
+// y (1 + e / 2 + 3 e^2 / 8), e = 1 - d y^2 (error O(e^3), so rounding-limited), folded into the
+// products that use it; the column is broadcast from before the diagonal lane's select, which
+// keeps the per-pivot dependency chain at about ten instructions.
+__device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c, int n) {
   // the first failing pivot classifies the tile (see the comment above)
   int kind = 0;
+  dinv = 1.0;  // rows of skipped padding pivots keep it
+  double dj = bc(h[0], 0), y = __builtin_amdgcn_rsq(dj);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double dj = bc(h[j], j);
-    const bool good = dj > 0.0 && dj <= 1.7976931348623157e308;
-    kind = kind ? kind : (good ? 0 : (isfinite(dj) ? 1 : 2));
-    dj = good ? dj : 1.0;
-    const double inv = rsqrt_f64(dj);
-    h[j] = (c == j) ? dj * inv : h[j] * inv;
-    dinv = (c == j) ? inv : dinv;
+  for (int j0 = 0; j0 < 16; j0 += 4) {
+    if (j0 < n) {
 #pragma unroll
-    for (int kk = j + 1; kk < 16; ++kk) h[kk] = fma(-h[j], bc(h[j], kk), h[kk]);
+      for (int j = j0; j < j0 + 4; ++j) {
+        const bool good = dj > 0.0 && dj <= 1.7976931348623157e308;
+        kind = kind ? kind : (good ? 0 : (isfinite(dj) ? 1 : 2));
+        const double t = dj * y;
+        const double e = fma(-t, y, 1.0);
+        const double corr = e * fma(e, 0.375, 0.5);
+        const double hy = h[j] * y;
+        // column j of L below the pivot (a failed pivot counts as 1: the column is kept)
+        const double hs = good ? fma(hy, corr, hy) : h[j];
+        const double dg = good ? fma(t, corr, t) : 1.0, di = good ? fma(y, corr, y) : 1.0;
+        // look-ahead: the next pivot's column first, and its 1/sqrt estimate, then the other
+        // updates, which issue while that estimate is in flight
+        if (j + 1 < 16) {
+          h[j + 1] = fma(-hs, bc(hs, j + 1), h[j + 1]);
+          dj = bc(h[j + 1], j + 1);
+          y = __builtin_amdgcn_rsq(dj);
+        }
+#pragma unroll
+        for (int kk = j + 2; kk < 16; ++kk) h[kk] = fma(-hs, bc(hs, kk), h[kk]);
+        h[j] = (c == j) ? dg : hs;
+        dinv = (c == j) ? di : dinv;
+      }
+    }
   }
   return kind;
 }
@@ -185,15 +206,23 @@ __device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c) {
 //   X[c][q] = dinv delta_cq - sum_{k<c} (dinv L[c][k]) X[k][q],
 // with the rows X[k] taken in order k = 0, 1, ... by row broadcasts (row k is final once the steps
 // before it are done).  Each lane group forms its own four columns; entries above the diagonal
-// are zero and stay zero, so all columns run the same steps.  Registers and DPP only.
-__device__ __forceinline__ void inv16_cols4(double (&x)[4], const double (&h)[16], double dinv, int c, int g) {
+// are zero and stay zero, so all columns run the same steps.  Registers and DPP only.  With n real
+// pivots (the rest identity padding, as in chol16) the steps k >= n - 1 change nothing.
+__device__ __forceinline__ void inv16_cols4(double (&x)[4], const double (&h)[16], double dinv, int c, int g, int n) {
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq) x[qq] = 4 * g + qq == c ? dinv : 0.0;
+  // steps in chunks of four under uniform branches, as in chol16 (extra steps on padding rows are
+  // exact no-ops: their multipliers are zero)
 #pragma unroll
-  for (int k = 0; k < 15; ++k) {
-    const double mk = k < c ? dinv * h[k] : 0.0;
+  for (int k0 = 0; k0 < 15; k0 += 4) {
+    if (k0 < n - 1) {
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) x[qq] = fma(-mk, bc(x[qq], k), x[qq]);
+      for (int k = k0; k < k0 + 4 && k < 15; ++k) {
+        const double mk = k < c ? dinv * h[k] : 0.0;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) x[qq] = fma(-mk, bc(x[qq], k), x[qq]);
+      }
+    }
   }
 }
 
@@ -485,11 +514,13 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
         for (int t = 0; t < 4; ++t) SC[MM<double>::row(t, g) * LD + c] = Gj[t];
         wave_sync();
         double dinv = 0.0;
+        // real pivots of the tile (the rest is padding)
+        const int nreal = __builtin_amdgcn_readfirstlane(min(16, j < TU ? nu - 16 * j : nx - 16 * (j - TU)));
         {
           double h[16];
 #pragma unroll
           for (int q = 0; q < 16; ++q) h[q] = SC[c * LD + q];
-          const int bad = chol16(h, dinv, c);
+          const int bad = chol16(h, dinv, c, nreal);
           if (bad && lane == 0 && s_info == 0) s_info = bad == 2 ? LQ_INFO_NONFINITE : k + 1;
           // U(j, j) = L_jj^T into its panel / the L^Q tiles
 #pragma unroll
@@ -500,11 +531,15 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
             else lqb(j - TU, j - TU)[q * LQ + c] = (TF)l;
           }
           if (g == 0) dv[16 * j + c] = dinv;
-          // X = L_jj^{-1}; DI holds X^T row-major (row q = column q of X: DI[q][c] = X[c][q])
-          double x[4];
-          inv16_cols4(x, h, dinv, c, g);
+          // X = L_jj^{-1}; DI holds X^T row-major (row q = column q of X: DI[q][c] = X[c][q]);
+          // the last tile column has no panel to the right of it and needs no inverse (at stage 0
+          // the last input tile still has the state columns' panels, L^S_0)
+          if (j + 1 < T) {
+            double x[4];
+            inv16_cols4(x, h, dinv, c, g, nreal);
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq) DI[(4 * g + qq) * LD + c] = x[qq];
+            for (int qq = 0; qq < 4; ++qq) DI[(4 * g + qq) * LD + c] = x[qq];
+          }
         }
         // column j is complete: none of its tiles is read again, and redefining them here lets
         // the diagonal step reuse their registers

@@ -159,7 +159,7 @@ int lq_plan_get_launch(const lq_plan* plan, lq_launch* cfg);
 /* Kernel variant of the factor sweep (the solve kernels follow from it):
  *   "small"    uniform batches with nx + nu <= 16 of an instantiated shape: 16 lanes per instance
  *   "tile"     nu <= 64 and ceil(nx/16) + ceil(nu/16) <= 10, any mode; with checkpoints
- *              nx <= 64, nu <= 64 and LQ_F64 / LQ_MIXED_F32: one workgroup per instance, stage
+ *              nx <= 64 and nu <= 64, or nx <= 128 and nu <= 32, any mode: one workgroup per instance, stage
  *              products and the blocked stage Cholesky on 16x16 matrix-core tiles (a
  *              checkpointed solve recomputes each segment with the same sweep in its workgroup)
  *   "generic"  any shape whose stage tile fits in LDS (nx + nu up to about 80)

@@ -53,7 +53,7 @@ int tsolve_blocks_per_cu(int NXP, int NUP, lq_mode mode);
 hipError_t launch_solve_tsolve(int NXP, int NUP, lq_mode mode, const SolveArgs& a, const GenericLaunch& c,
                                hipStream_t st);
 
-// Checkpointed solve kernels of tile plans, nx <= 64, nu <= 64 (lq_tckpt.hip).
+// Checkpointed solve kernels of tile plans, nx <= 64 with nu <= 64 or nx <= 128 with nu <= 32 (lq_tckpt.hip).
 bool tckpt_sizes(int maxnx, int maxnu, int* NXP, int* NUP);
 bool tckpt_mode_supported(lq_mode mode);
 int tckpt_waves(int NXP, int NUP);
@@ -344,7 +344,10 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   }
   // Raise the dynamic-LDS limits of the kernels the plan may use.  A refused request only removes
   // that variant; its error is consumed here so that it does not surface at a later HIP call.
-  if (lq::prepare_generic(false, p->lds_solve) != hipSuccess) {
+  if (p->variant == VAR_TILE && ckpt_stride > 0 && !p->can_generic) {
+    // a checkpointed tile plan solves with its own kernel: the generic solve kernels, whose LDS
+    // would hold the generic factor scratch beside the stage (beyond the limit here), are not used
+  } else if (lq::prepare_generic(false, p->lds_solve) != hipSuccess) {
     (void)hipGetLastError();
     const size_t need_solve = p->lds_solve;
     (void)hipFree(p->desc_d);  // cleanup of a failed creation

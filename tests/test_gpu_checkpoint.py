@@ -94,8 +94,14 @@ def _blocks(ws, fbytes, fs, first, count):
     return v[first * fs:(first + count) * fs].reshape(count, fs)
 
 
-@pytest.mark.parametrize("nx,nu", [(32, 8), (40, 20), (12, 50)])
-@pytest.mark.parametrize("mode", ["f64", "mixed_f32"])
+def _waves(t):
+    # wavefronts of the tile factor sweep for t tile columns (3, 5 or 10)
+    return 3 if t <= 3 else 5 if t <= 5 else 10
+
+
+@pytest.mark.parametrize("nx,nu,mode", [(32, 8, "f64"), (40, 20, "f64"), (12, 50, "f64"), (32, 8, "mixed_f32"),
+                                        (40, 20, "mixed_f32"), (12, 50, "mixed_f32"), (100, 20, "f64"),
+                                        (100, 20, "mixed_bf16"), (40, 20, "mixed_bf16")])
 def test_tile_recomputed_blocks_are_bit_identical(nx, nu, mode):
     """One instance, N = 23, s = 5: the checkpoint slots written by the factor kernel are the
     blocks of the full sweep (where both use one wavefront count), and the segment the solve
@@ -103,20 +109,25 @@ def test_tile_recomputed_blocks_are_bit_identical(nx, nu, mode):
     sweep's blocks and its own checkpoint slot 20, bit for bit."""
     print(f"case: tile recomputed blocks nx={nx} nu={nu} {mode}", flush=True)
     N, s = 23, 5
-    p = synth.random_problem(800 + nx + nu, N, nx, nu)
+    # wide states: the large-state generator (stable dynamics; I + 0.3 G would grow like 4^k at nx = 100)
+    p = synth.make_instance(4, 0, N=N, nx=nx, nu=nu) if nx > 64 else synth.random_problem(800 + nx + nu, N, nx, nu)
     fbytes = 8 if mode == "f64" else 4
     fs = nu * (nu + 1) // 2 + nu + nx * nu + nx * (nx + 1) // 2 + nx
     full = run([p], mode, max_it=0, plan=L.Plan([N], [nx], [nu], mode=mode))
     plan = L.Plan([N], [nx], [nu], mode=mode, ckpt_stride=s)
     assert plan.variant == "tile"
     ck = run([p], mode, max_it=0, plan=plan)
-    assert ck["info"][0] == 0 and ck["rel"][0] <= (1e-10 if mode == "f64" else 1e-3)
+    assert ck["info"][0] == 0 and ck["rel"][0] <= {"f64": 1e-10, "mixed_f32": 1e-3, "mixed_bf16": 1.0}[mode]
     F = _blocks(full["ws"], fbytes, fs, 0, N + 1)
     nslots = N // s + 2                     # stages 0, 5, 10, 15, 20 and N
     slots = _blocks(ck["ws"], fbytes, fs, 0, nslots)
     seg = _blocks(ck["ws"], fbytes, fs, nslots, N - 20)
     assert np.array_equal(seg[0], slots[4])
-    same_waves = (nx + 15) // 16 + (nu + 15) // 16 <= 3 or full["plan"].variant != "tile"
+    # the checkpointed plan's factor sweep runs with the wavefront count of the padded sizes
+    nxp = 32 if nx <= 32 else 64 if nx <= 64 else 128
+    nup = 16 if nu <= 16 else 32 if nu <= 32 else 64
+    same_waves = (_waves((nx + 15) // 16 + (nu + 15) // 16) == _waves(nxp // 16 + nup // 16)
+                  or full["plan"].variant != "tile")
     olq = nu * (nu + 1) // 2 + nu + nx * nu  # stage 0 leaves its L^Q part unwritten
     if same_waves:
         assert np.array_equal(slots[0][:olq], F[0][:olq])
@@ -194,3 +205,24 @@ def test_tile_checkpointed_ragged_batch(mode, max_it):
         sol = instance_solution(res, i)
         assert kkt.residual(p, *sol)[1] <= 1e-10, i
         assert forward_error(sol, oracle_solution(p)) <= 1e-9, i
+
+
+@pytest.mark.parametrize("mode,max_it", [("f64", 0), ("mixed_f32", 8), ("mixed_bf16", 12)])
+def test_tile_checkpointed_wide_state_and_bf16(mode, max_it):
+    """Checkpointed tile plans at padded nx 128 (nx = 100, nu = 20: nine tile columns) in every
+    mode, bf16 products included: against the oracle, the oracle's residual and the same plan
+    without checkpoints (whose factor sweep uses the same wavefront count, so the factor blocks
+    agree bit for bit and the solutions to rounding)."""
+    print(f"case: tile checkpoint nx=100 nu=20 {mode}", flush=True)
+    b = synth.make_batch(4, batch=2, N=12, nx=100, nu=20)
+    full = run(b, mode, max_it=max_it, plan=_tile_plan(b, mode, 0))
+    ck = run(b, mode, max_it=max_it, plan=_tile_plan(b, mode, 5))
+    assert ck["plan"].variant == "tile"
+    assert np.all(ck["info"] == 0) and ck["rel"].max() <= 1e-10, (ck["info"], ck["rel"])
+    assert ck["plan"].workspace_bytes < full["plan"].workspace_bytes
+    bar = 1e-11 if mode == "f64" else 1e-9
+    for i in range(b.batch):
+        sol = instance_solution(ck, i)
+        assert kkt.residual(b.instance(i), *sol)[1] <= 1e-10, i
+        assert forward_error(sol, oracle_solution(b.instance(i))) <= 1e-9, i
+        assert forward_error(sol, instance_solution(full, i)) <= bar, i

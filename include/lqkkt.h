@@ -158,12 +158,18 @@ int lq_plan_get_launch(const lq_plan* plan, lq_launch* cfg);
 
 /* Kernel variant of the factor sweep (the solve kernels follow from it):
  *   "small"    uniform batches with nx + nu <= 16 of an instantiated shape: 16 lanes per instance
+ *   "small_padded"  the other uniform batches with nx + nu <= 16 (float64 and float32 modes, no
+ *              checkpoints): the data padded on the device to the smallest instantiated shape that
+ *              covers it (extra states and inputs with identity cost and no coupling, whose solution
+ *              is zero), solved there, the outputs and factor blocks copied back; its workspace
+ *              also holds the padded copies (lq_solve reads the ones lq_factor made);
+ *              lq_factor_update refuses such plans
  *   "tile"     nu <= 64 and ceil(nx/16) + ceil(nu/16) <= 10, any mode; with checkpoints
  *              nx <= 64 and nu <= 64, or nx <= 128 and nu <= 32, any mode: one workgroup per instance, stage
  *              products and the blocked stage Cholesky on 16x16 matrix-core tiles (a
  *              checkpointed solve recomputes each segment with the same sweep in its workgroup)
  *   "generic"  any shape whose stage tile fits in LDS (nx + nu up to about 80)
- * A plan starts with the first of small, tile, generic that can take it.  lq_plan_variant returns
+ * A plan starts with the first of small, small_padded, tile, generic that can take it.  lq_plan_variant returns
  * the current name (static string); lq_plan_set_variant selects another one (LQ_EUNSUPPORTED if it
  * cannot take the plan, LQ_EINVAL for an unknown name).  All variants produce the same workspace
  * layout and agree to rounding. */

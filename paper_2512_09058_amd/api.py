@@ -100,7 +100,8 @@ class Plan:
         return sub
 
     def set_variant(self, name: str):
-        """Select the factor kernel variant ("small", "tile" or "generic"; see lq_plan_set_variant)."""
+        """Select the factor kernel variant ("small", "small_padded", "tile" or "generic"; see
+        lq_plan_set_variant)."""
         lib = _lib.load()
         check(lib.lq_plan_set_variant(self._h, name.encode()), "lq_plan_set_variant")
         self.variant = lib.lq_plan_variant(self._h).decode()

@@ -119,7 +119,7 @@ def lq_solve(A, B, Q, R, q, r, x0, S=None, f=None, mode: str = "f64", tol: float
              check: bool = True):
     """Differentiable batched LQ KKT solve (see module docstring for shapes).  ckpt_stride > 0
     keeps only every ckpt_stride-th cost-to-go factor between forward and backward and recomputes
-    the rest segment by segment.  variant selects the factor kernel ("small", "tile", "generic";
+    the rest segment by segment.  variant selects the factor kernel ("small", "small_padded", "tile", "generic";
     default: the plan's choice).  check: raise SolveError on a failed instance (module docstring)."""
     if max_it is None:
         max_it = 0 if mode == "f64" else 10

@@ -34,6 +34,12 @@ bool small_aligned(const lq_data& d, const void* ws);
 hipError_t launch_factor_small(lq_mode mode, int batch, int N, int nx, int nu, const lq_data& d,
                                void* F, double* V, int32_t* info, hipStream_t st);
 hipError_t launch_solve_small(lq_mode mode, int N, int nx, int nu, const SolveArgs& a, hipStream_t st);
+// Smallest compiled size-specialised shape covering (nx, nu) (lq_small.hip).
+bool small_envelope(lq_mode mode, int nx, int nu, int* NX, int* NU);
+// Copies to and from a padded problem, real factor blocks from padded ones (lq_pad.hip).
+hipError_t launch_pad(const PadOp* ops, int n, hipStream_t st);
+hipError_t launch_extract_small_factors(bool f64, const void* src, void* dst, int64_t blocks, int nx, int nu, int NX,
+                                        int NU, hipStream_t st);
 
 // Matrix-core tile factor kernels (lq_tile.hip).
 int tile_max_columns();
@@ -119,7 +125,7 @@ void clear_error() { g_err.clear(); }
 
 static const size_t kLdsLimit = 160 * 1024;
 
-enum Variant : int32_t { VAR_GENERIC = 0, VAR_SMALL = 1, VAR_TILE = 2 };
+enum Variant : int32_t { VAR_GENERIC = 0, VAR_SMALL = 1, VAR_TILE = 2, VAR_SMALL_PAD = 3 };
 
 struct lq_plan {
   int32_t batch = 0;
@@ -164,6 +170,15 @@ struct lq_plan {
   int cu_count = 0;
   lq_launch launch = {128, 0, 0, 0};
   int32_t grid_factor = 0, grid_solve = 0;  // persistent grid sizes for `launch`
+  // Uniform plans whose shape has no size-specialised kernel but fits in a compiled one
+  // (VAR_SMALL_PAD): the plan of that padded shape, whose workspace follows this plan's regions at
+  // offPad, then the padded data and outputs (A, B, Q, R, S, q, r, f, x0, x, u, lam).
+  bool can_small_pad = false;
+  int pad_nx = 0, pad_nu = 0;
+  lq_plan* inner = nullptr;
+  size_t offPad = 0;
+  size_t offPadArr[12] = {};
+  ~lq_plan() { lq_plan_destroy(inner); }
 };
 
 // Persistent grid sizes for the plan's launch shape (host queries; done outside the calls so
@@ -311,6 +326,34 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   p->offZB = align256(p->offV2 + (size_t)aV2 * sizeof(double));
   p->offCtr = align256(p->offZB + (size_t)aZB * sizeof(double));
   p->ws_bytes = p->offCtr + 256;
+  // a uniform shape without a size-specialised kernel of its own runs padded to the smallest
+  // compiled shape that covers it (identity cost, no coupling on the padding; see lq_pad.hip)
+  int env_nx = 0, env_nu = 0;
+  if (p->uniform && ckpt_stride == 0 && !p->can_small && lq::small_envelope(mode, nx[0], nu[0], &env_nx, &env_nu)) {
+    std::vector<int32_t> en(batch, env_nx), eu(batch, env_nu);
+    lq_plan* in = nullptr;
+    if (lq_plan_create(batch, N, en.data(), eu.data(), mode, 0, &in) == LQ_OK && in->variant == VAR_SMALL) {
+      const int64_t b = batch, n = N[0], X = env_nx, U = env_nu;
+      const int64_t elems[12] = {b * n * X * X, b * n * X * U, b * (n + 1) * X * X, b * n * U * U, b * n * U * X,
+                                 b * (n + 1) * X, b * n * U, b * n * X, b * X, b * n * X, b * n * U, b * n * X};
+      size_t o = align256(p->ws_bytes);
+      p->offPad = o;
+      o = align256(o + in->ws_bytes);
+      for (int k = 0; k < 12; ++k) {
+        p->offPadArr[k] = o;
+        o = align256(o + (size_t)elems[k] * sizeof(double));
+      }
+      p->ws_bytes = o;
+      p->inner = in;
+      p->pad_nx = env_nx;
+      p->pad_nu = env_nu;
+      p->can_small_pad = true;
+      p->variant = VAR_SMALL_PAD;
+    } else {
+      lq_plan_destroy(in);
+    }
+    g_err.clear();
+  }
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(LQ_EHIP, "lq_plan_create: hipGetDevice failed");
@@ -479,8 +522,13 @@ extern "C" int lq_plan_create_subset(const lq_plan* parent, int32_t n, const int
     for (int a = 0; a < LQ_ARR_COUNT; ++a) p->off[a][i] = parent->off[a][idx[i]];
   }
   for (int a = 0; a < LQ_ARR_COUNT; ++a) p->total[a] = parent->total[a];
-  p->can_small = false;
-  if (p->variant == VAR_SMALL) p->variant = p->can_tile ? VAR_TILE : VAR_GENERIC;
+  p->can_small = p->can_small_pad = false;
+  if (p->inner) {  // the padded copies would address the parent's arrays as a dense batch
+    lq_plan_destroy(p->inner);
+    p->inner = nullptr;
+    p->ws_bytes = p->offPad;
+  }
+  if (p->variant == VAR_SMALL || p->variant == VAR_SMALL_PAD) p->variant = p->can_tile ? VAR_TILE : VAR_GENERIC;
   if (p->variant == VAR_GENERIC && !p->can_generic) {
     lq_plan_destroy(p);
     return fail(LQ_EUNSUPPORTED, "%s: no descriptor-addressed kernel takes these sizes", fn);
@@ -591,7 +639,10 @@ extern "C" int64_t lq_plan_offsets(const lq_plan* p, lq_array which, int64_t* of
 
 extern "C" const char* lq_plan_variant(const lq_plan* p) {
   if (!p) return "";
-  return p->variant == VAR_SMALL ? "small" : p->variant == VAR_TILE ? "tile" : "generic";
+  return p->variant == VAR_SMALL       ? "small"
+         : p->variant == VAR_SMALL_PAD ? "small_padded"
+         : p->variant == VAR_TILE      ? "tile"
+                                       : "generic";
 }
 
 extern "C" int lq_plan_set_variant(lq_plan* p, const char* name) {
@@ -600,6 +651,7 @@ extern "C" int lq_plan_set_variant(lq_plan* p, const char* name) {
   Variant v;
   bool ok;
   if (!strcmp(name, "small")) { v = VAR_SMALL; ok = p->can_small; }
+  else if (!strcmp(name, "small_padded")) { v = VAR_SMALL_PAD; ok = p->can_small_pad; }
   else if (!strcmp(name, "tile")) { v = VAR_TILE; ok = p->can_tile; }
   else if (!strcmp(name, "generic")) { v = VAR_GENERIC; ok = p->can_generic; }
   else return fail(LQ_EINVAL, "lq_plan_set_variant: unknown variant '%s'", name);
@@ -627,12 +679,58 @@ static int launch_status(hipError_t e, const char* fn) {
   return LQ_OK;
 }
 
+// Padded copies of a VAR_SMALL_PAD plan's data in its workspace (S and f as given: present or NULL).
+static lq_data padded_data(const lq_plan* p, const lq_data* d, char* w) {
+  lq_data pd;
+  pd.A = (const double*)(w + p->offPadArr[0]);
+  pd.B = (const double*)(w + p->offPadArr[1]);
+  pd.Q = (const double*)(w + p->offPadArr[2]);
+  pd.R = (const double*)(w + p->offPadArr[3]);
+  pd.S = d->S ? (const double*)(w + p->offPadArr[4]) : nullptr;
+  pd.q = (const double*)(w + p->offPadArr[5]);
+  pd.r = (const double*)(w + p->offPadArr[6]);
+  pd.f = d->f ? (const double*)(w + p->offPadArr[7]) : nullptr;
+  pd.x0 = (const double*)(w + p->offPadArr[8]);
+  return pd;
+}
+
+// lq_factor of a VAR_SMALL_PAD plan: the data padded to the compiled shape, the inner plan's factor
+// (its factors, sweep vectors and the padded data stay in this plan's workspace for lq_solve), and
+// the factor blocks copied out into this plan's own layout, the one every variant writes (the
+// adjoint then runs on the descriptor-addressed kernels, as for size-specialised plans).
+static int factor_padded(const lq_plan* p, const lq_data* d, char* w, int32_t* info, hipStream_t st) {
+  const int64_t b = p->batch, n = p->N[0];
+  const int x = p->nx[0], u = p->nu[0], X = p->pad_nx, U = p->pad_nu;
+  lq::PadOp ops[9];
+  int k = 0;
+  auto add = [&](const double* src, int arr, int64_t blocks, int r, int c, int R, int C, double diag) {
+    ops[k++] = lq::PadOp{src, (double*)(w + p->offPadArr[arr]), blocks, r, c, R, C, diag, 0};
+  };
+  add(d->A, 0, b * n, x, x, X, X, 0.0);
+  add(d->B, 1, b * n, x, u, X, U, 0.0);
+  add(d->Q, 2, b * (n + 1), x, x, X, X, 1.0);
+  add(d->R, 3, b * n, u, u, U, U, 1.0);
+  if (d->S) add(d->S, 4, b * n, u, x, U, X, 0.0);
+  add(d->q, 5, b * (n + 1), 1, x, 1, X, 0.0);
+  add(d->r, 6, b * n, 1, u, 1, U, 0.0);
+  if (d->f) add(d->f, 7, b * n, 1, x, 1, X, 0.0);
+  add(d->x0, 8, b, 1, x, 1, X, 0.0);
+  int rc = launch_status(lq::launch_pad(ops, k, st), "lq_factor");
+  if (rc) return rc;
+  const lq_data pd = padded_data(p, d, w);
+  if ((rc = lq_factor(p->inner, &pd, w + p->offPad, info, st))) return rc;
+  return launch_status(lq::launch_extract_small_factors(p->mode == LQ_F64, w + p->offPad + p->inner->offF,
+                                                        w + p->offF, b * (n + 1), x, u, X, U, st),
+                       "lq_factor");
+}
+
 extern "C" int lq_factor(const lq_plan* p, const lq_data* d, void* ws, int32_t* info, hipStream_t st) {
   g_err.clear();
   int rc = check_common(p, d, ws, "lq_factor");
   if (rc) return rc;
   if (!info) return fail(LQ_EINVAL, "lq_factor: info is NULL");
   char* w = (char*)ws;
+  if (p->variant == VAR_SMALL_PAD) return factor_padded(p, d, w, info, st);
   void* F = w + p->offF;
   double* V = (double*)(w + p->offV);
   hipError_t e;
@@ -705,6 +803,21 @@ extern "C" int lq_solve(const lq_plan* p, const lq_data* d, void* ws, const lq_s
   if ((rc = check_opts(o, "lq_solve"))) return rc;
   if (!x || !u || !lam) return fail(LQ_EINVAL, "lq_solve: x, u, lam are required");
   if (!info) return fail(LQ_EINVAL, "lq_solve: info is NULL");
+  if (p->variant == VAR_SMALL_PAD) {
+    // the inner plan's solve on the padded data lq_factor left in the workspace, then the real
+    // rows of x, u, lam (rel_res, iters and info are those of the padded problem, the same values)
+    char* w = (char*)ws;
+    const lq_data pd = padded_data(p, d, w);
+    double* xp = (double*)(w + p->offPadArr[9]);
+    double* up = (double*)(w + p->offPadArr[10]);
+    double* lp = (double*)(w + p->offPadArr[11]);
+    if ((rc = lq_solve(p->inner, &pd, w + p->offPad, o, xp, up, lp, rel_res, iters, info, st))) return rc;
+    const int64_t bn = (int64_t)p->batch * p->N[0];
+    const int x_ = p->nx[0], u_ = p->nu[0], X = p->pad_nx, U = p->pad_nu;
+    const lq::PadOp ops[3] = {{xp, x, bn, 1, x_, 1, X, 0.0, 1}, {up, u, bn, 1, u_, 1, U, 0.0, 1},
+                              {lp, lam, bn, 1, x_, 1, X, 0.0, 1}};
+    return launch_status(lq::launch_pad(ops, 3, st), "lq_solve");
+  }
   lq::SolveArgs a = base_args(p, d, ws, o);
   a.x = x; a.u = u; a.lam = lam;
   a.rhs = lq::RHS_PRIMAL;
@@ -812,6 +925,8 @@ extern "C" int lq_factor_update(const lq_plan* p, const lq_data* d, const lq_upd
   if ((rc = check_update_rows(p, u, fn))) return rc;
   if (p->mode != LQ_F64 || p->ckpt != 0)
     return fail(LQ_EUNSUPPORTED, "%s: updates need a float64 plan without checkpoints", fn);
+  if (p->variant == VAR_SMALL_PAD)
+    return fail(LQ_EUNSUPPORTED, "%s: the factors of a small_padded plan are kept padded; select another variant", fn);
   const UpdSizes z = update_sizes(p);
   const bool rows = u && u->m > 0;
   if (!lq::update_sweep_fits(z.fs, p->maxnx + p->maxnu, p->maxnx) || (rows && z.wmax <= 0))

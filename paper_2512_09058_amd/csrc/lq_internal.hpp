@@ -23,6 +23,19 @@ struct Desc {
 // Factor block of one stage (elements): [LR packed lower, nu(nu+1)/2][1/diag LR, nu]
 // [LS, nx*nu row-major][LQ packed lower, nx(nx+1)/2][1/diag LQ, nx].  Stage N holds only
 // the LQ part (chol Q_N); stage 0 leaves the LQ part unused.
+// One copy: `blocks` row-major blocks of r x c elements (the source of a pad, the destination of
+// an unpad) and R x C elements (the other side); padding entries of a pad get `diag` on the
+// diagonal and 0 elsewhere.
+struct PadOp {
+  const double* src;
+  double* dst;
+  int64_t blocks;
+  int32_t r, c, R, C;
+  double diag;
+  int32_t unpad;
+};
+constexpr int kPadOps = 12;
+
 __host__ __device__ inline int64_t stage_factor_elems(int nx, int nu) {
   return (int64_t)nu * (nu + 1) / 2 + nu + (int64_t)nx * nu + (int64_t)nx * (nx + 1) / 2 + nx;
 }

@@ -27,12 +27,12 @@ def candidates(plan: api.Plan):
     """(variant, launch) pairs the plan can run; the plan's current variant is kept."""
     out = []
     current = plan.variant
-    for v in ("small", "tile", "generic"):
+    for v in ("small", "small_padded", "tile", "generic"):
         try:
             plan.set_variant(v)
         except RuntimeError:
             continue
-        if v == "small":
+        if v in ("small", "small_padded"):
             out.append({"variant": v, "launch": plan.get_launch()})
         elif v == "tile":
             out += [{"variant": v, "launch": {"threads": 128, "persistent": p, "blocks_per_cu": b}}

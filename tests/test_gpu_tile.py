@@ -170,10 +170,11 @@ def test_large_workload_full_size_sampled():
 
 
 def test_bf16_plans_only_where_the_tile_kernel_runs():
-    """The bf16 mode exists only on the matrix-core tile kernel: checkpointed plans and shapes it
-    does not take are refused instead of silently running float32 products."""
+    """The bf16 mode exists only on the matrix-core tile kernels (checkpointed ones included):
+    shapes they do not take are refused instead of silently running float32 products."""
+    assert L.Plan(20, 12, 4, batch=2, mode="mixed_bf16", ckpt_stride=5).variant == "tile"
     with pytest.raises(RuntimeError, match="status -2"):
-        L.Plan(20, 12, 4, batch=2, mode="mixed_bf16", ckpt_stride=5)
+        L.Plan(20, 100, 40, batch=2, mode="mixed_bf16", ckpt_stride=5)
     with pytest.raises(RuntimeError, match="status -2"):
         L.Plan(20, 170, 4, batch=2, mode="mixed_bf16")
     plan = L.Plan(20, 12, 4, batch=2, mode="mixed_bf16")

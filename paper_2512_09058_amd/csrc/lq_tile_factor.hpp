@@ -246,6 +246,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
                                                   const TF* __restrict__ from, double* __restrict__ Vi,
                                                   unsigned char* lds, int& s_info) {
   constexpr bool F64 = std::is_same<TP, double>::value;
+  constexpr bool EARLY_IN = TMAX <= 5;  // input side of a stage inside its potrf (see input_side)
   typedef typename MM<TP>::V PV;
   typedef typename Elem<TP>::type TE;  // W slabs, converted C fragments
   constexpr int LQ = Ld<TF>::v, LW = Ld<TE>::v, LD = Ld<double>::v;
@@ -497,6 +498,61 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
       }
     }
 
+    // ---- the input side of stage k, by wavefront 0 alone once the last input pivot tile is done
+    // (up to five tile columns; with more, wavefront 0 alone would take longer than the state
+    // pivots' slot and share its SIMD with them: there it runs after the potrf on every wavefront)
+    // (L^R_k, L^S_k and their diagonal are final then and no later pivot touches their panels;
+    // wavefront 0 has no later pivot work, so this runs beside the state pivots):
+    //   rbar_k = (L^R_k)^{-1} rhat,  p_k = qhat - L^S_k rbar_k (rounded factors, float64),
+    //   and the L^R_k, 1/diag L^R_k, L^S_k parts of the stage's factor block.
+    auto input_side = [&]() {
+      if (rhs) {
+        // one row per lane, 64 rows per pass
+        for (int i0 = 0; i0 < nu; i0 += 64) {
+          const int i = i0 + lane;
+          double acc = i < nu ? rq[i] : 0.0;
+          const double di = i < nu ? (double)(TF)dv[i] : 0.0;
+          // contributions of the rows of earlier passes
+          for (int jj = 0; jj < i0; ++jj)
+            if (i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * rb[jj];
+          // (the coefficient is read on every lane, at a clamped row, and applied through a select:
+          // a read under a condition waits for itself at once)
+          const int ic = min(i, nu - 1);
+          for (int jj = i0; jj < nu && jj < i0 + 64; ++jj) {
+            const double y = lane_bcast(acc * di, jj - i0);
+            const double lv = (double)(TF)upan(jj >> 4, ic >> 4)[(jj & 15) * LD + (ic & 15)];
+            acc = (i > jj && i < nu) ? acc - lv * y : acc;
+          }
+          if (i < nu) {
+            const double v = acc * di;
+            rb[i] = v;
+            rbar_g[(int64_t)k * nu + i] = v;
+          }
+          wave_sync();
+        }
+        if (k > 0) {
+          for (int i = lane; i < nx; i += 64) {
+            double s = rq[16 * TU + i];
+            for (int jj = 0; jj < nu; ++jj)
+              s -= (double)(TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)] * rb[jj];
+            pv[i] = s;
+            p_g[(int64_t)k * nx + i] = s;
+          }
+        }
+      }
+      TF* Fi = dst(k);
+      if (Fi) {
+        for (int i = 0; i < nu; ++i)
+          for (int jj = lane; jj <= i; jj += 64)
+            Fi[i * (i + 1) / 2 + jj] = (TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)];
+        for (int i = lane; i < nu; i += 64) Fi[oDR + i] = (TF)dv[i];
+        for (int e = lane; e < nx * nu; e += 64) {
+          const int i = e / nu, jj = e - i * nu;
+          Fi[oLS + e] = (TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)];
+        }
+      }
+    };
+
     // ---- blocked potrf over the pivot tiles [j0, j1)
     const int j0 = k == N ? TU : 0, j1 = k == 0 ? TU : T;
     for (int j = j0; j < j1; ++j) {
@@ -564,6 +620,9 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
         }
       }
       __syncthreads();
+      if constexpr (EARLY_IN) {
+        if (k < N && j == TU - 1 && w == 0) input_side();
+      }
       if (own && a > j) {
 #pragma unroll
         for (int bb = 0; bb < TMAX; ++bb)
@@ -572,56 +631,60 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
     }
     __syncthreads();
 
-    // ---- rbar_k = (L^R_k)^{-1} rhat,  p_k = qhat - L^S_k rbar_k (rounded factors, float64)
-    if (rhs && k < N) {
-      if (w == 0) {
-        // one row per lane, 64 rows per pass
-        for (int i0 = 0; i0 < nu; i0 += 64) {
-          const int i = i0 + lane;
-          double acc = i < nu ? rq[i] : 0.0;
-          const double di = i < nu ? (double)(TF)dv[i] : 0.0;
-          // contributions of the rows of earlier passes
-          for (int jj = 0; jj < i0; ++jj)
-            if (i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * rb[jj];
-          // (the coefficient is read on every lane, at a clamped row, and applied through a select:
-          // a read under a condition waits for itself at once)
-          const int ic = min(i, nu - 1);
-          for (int jj = i0; jj < nu && jj < i0 + 64; ++jj) {
-            const double y = lane_bcast(acc * di, jj - i0);
-            const double lv = (double)(TF)upan(jj >> 4, ic >> 4)[(jj & 15) * LD + (ic & 15)];
-            acc = (i > jj && i < nu) ? acc - lv * y : acc;
+    if constexpr (!EARLY_IN) {
+      // ---- rbar_k = (L^R_k)^{-1} rhat,  p_k = qhat - L^S_k rbar_k (rounded factors, float64)
+      if (rhs && k < N) {
+        if (w == 0) {
+          // one row per lane, 64 rows per pass
+          for (int i0 = 0; i0 < nu; i0 += 64) {
+            const int i = i0 + lane;
+            double acc = i < nu ? rq[i] : 0.0;
+            const double di = i < nu ? (double)(TF)dv[i] : 0.0;
+            // contributions of the rows of earlier passes
+            for (int jj = 0; jj < i0; ++jj)
+              if (i < nu) acc -= (double)(TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)] * rb[jj];
+            // (the coefficient is read on every lane, at a clamped row, and applied through a select:
+            // a read under a condition waits for itself at once)
+            const int ic = min(i, nu - 1);
+            for (int jj = i0; jj < nu && jj < i0 + 64; ++jj) {
+              const double y = lane_bcast(acc * di, jj - i0);
+              const double lv = (double)(TF)upan(jj >> 4, ic >> 4)[(jj & 15) * LD + (ic & 15)];
+              acc = (i > jj && i < nu) ? acc - lv * y : acc;
+            }
+            if (i < nu) {
+              const double v = acc * di;
+              rb[i] = v;
+              rbar_g[(int64_t)k * nu + i] = v;
+            }
+            wave_sync();
           }
-          if (i < nu) {
-            const double v = acc * di;
-            rb[i] = v;
-            rbar_g[(int64_t)k * nu + i] = v;
+        }
+        __syncthreads();
+        if (k > 0) {
+          for (int i = tid; i < nx; i += nt) {
+            double s = rq[16 * TU + i];
+            for (int jj = 0; jj < nu; ++jj)
+              s -= (double)(TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)] * rb[jj];
+            pv[i] = s;
+            p_g[(int64_t)k * nx + i] = s;
           }
-          wave_sync();
         }
       }
-      __syncthreads();
-      if (k > 0) {
-        for (int i = tid; i < nx; i += nt) {
-          double s = rq[16 * TU + i];
-          for (int jj = 0; jj < nu; ++jj)
-            s -= (double)(TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)] * rb[jj];
-          pv[i] = s;
-          p_g[(int64_t)k * nx + i] = s;
+      // ---- input part of the factor block of stage k (coalesced, from LDS)
+      if (TF* Fk = dst(k); Fk && k < N) {
+        for (int i = w; i < nu; i += nt >> 6)
+          for (int jj = lane; jj <= i; jj += 64)
+            Fk[i * (i + 1) / 2 + jj] = (TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)];
+        for (int i = tid; i < nu; i += nt) Fk[oDR + i] = (TF)dv[i];
+        for (int e = tid; e < nx * nu; e += nt) {
+          const int i = e / nu, jj = e - i * nu;
+          Fk[oLS + e] = (TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)];
         }
       }
     }
-    // ---- factor block of stage k (coalesced, from LDS)
+    // ---- factor block of stage k, state part (coalesced, from LDS; the input part went out with
+    // the right-hand-side step)
     TF* Fk = dst(k);
-    if (Fk && k < N) {
-      for (int i = w; i < nu; i += nt >> 6)
-        for (int jj = lane; jj <= i; jj += 64)
-          Fk[i * (i + 1) / 2 + jj] = (TF)upan(jj >> 4, i >> 4)[(jj & 15) * LD + (i & 15)];
-      for (int i = tid; i < nu; i += nt) Fk[oDR + i] = (TF)dv[i];
-      for (int e = tid; e < nx * nu; e += nt) {
-        const int i = e / nu, jj = e - i * nu;
-        Fk[oLS + e] = (TF)upan(jj >> 4, TU + (i >> 4))[(jj & 15) * LD + (i & 15)];
-      }
-    }
     if (Fk && k > 0) {
       for (int i = w; i < nx; i += nt >> 6)
         for (int jj = lane; jj <= i; jj += 64)

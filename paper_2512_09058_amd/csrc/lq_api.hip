@@ -329,7 +329,9 @@ extern "C" int lq_plan_create(int32_t batch, const int32_t* N, const int32_t* nx
   // a uniform shape without a size-specialised kernel of its own runs padded to the smallest
   // compiled shape that covers it (identity cost, no coupling on the padding; see lq_pad.hip)
   int env_nx = 0, env_nu = 0;
-  if (p->uniform && ckpt_stride == 0 && !p->can_small && lq::small_envelope(mode, nx[0], nu[0], &env_nx, &env_nu)) {
+  // (32-bit row indices in the copy kernels: the padded arrays stay below 2^31 / 16 rows)
+  if (p->uniform && ckpt_stride == 0 && !p->can_small && (int64_t)batch * (N[0] + 1) * 16 < ((int64_t)1 << 27) &&
+      lq::small_envelope(mode, nx[0], nu[0], &env_nx, &env_nu)) {
     std::vector<int32_t> en(batch, env_nx), eu(batch, env_nu);
     lq_plan* in = nullptr;
     if (lq_plan_create(batch, N, en.data(), eu.data(), mode, 0, &in) == LQ_OK && in->variant == VAR_SMALL) {

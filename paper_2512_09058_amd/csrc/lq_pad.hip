@@ -21,24 +21,24 @@ struct PadOps {
 
 // Grid: x strides over the destination rows of the largest copy (16 lanes per row: C, c <= 16),
 // y = the copy.  Coalesced destination writes; the source rows are read where they overlap.
+// 32-bit row indices (the plan keeps every padded array below 2^31 rows): a 64-bit division per
+// element would cost more than the element's memory traffic.
 __global__ void __launch_bounds__(256) k_pad(PadOps ops) {
   const PadOp o = ops.op[blockIdx.y];
-  const int dr = o.unpad ? o.r : o.R, dc = o.unpad ? o.c : o.C;  // destination block shape
-  const int sc = o.unpad ? o.C : o.c;                             // source row length
-  const int64_t rows = o.blocks * dr;
-  const int j = threadIdx.x & 15;
-  for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4; row < rows;
-       row += ((int64_t)gridDim.x * blockDim.x) >> 4) {
+  const uint32_t dr = o.unpad ? o.r : o.R, dc = o.unpad ? o.c : o.C;  // destination block shape
+  const uint32_t sc = o.unpad ? o.C : o.c;                             // source row length
+  const uint32_t srows = o.unpad ? o.R : o.r;
+  const uint32_t rows = (uint32_t)(o.blocks * dr);
+  const uint32_t j = threadIdx.x & 15;
+  for (uint32_t row = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; row < rows; row += (gridDim.x * blockDim.x) >> 4) {
     if (j >= dc) continue;
-    const int64_t blk = row / dr;
-    const int i = (int)(row - blk * dr);
-    const int srows = o.unpad ? o.R : o.r;
+    const uint32_t blk = row / dr, i = row - blk * dr;
     double v;
-    if (o.unpad || (i < o.r && j < o.c))
-      v = o.src[(blk * srows + i) * sc + j];
+    if (o.unpad || (i < (uint32_t)o.r && j < (uint32_t)o.c))
+      v = o.src[((uint64_t)blk * srows + i) * sc + j];
     else
       v = i == j ? o.diag : 0.0;
-    o.dst[row * dc + j] = v;
+    o.dst[(uint64_t)row * dc + j] = v;
   }
 }
 
@@ -47,24 +47,22 @@ __global__ void __launch_bounds__(256) k_pad(PadOps ops) {
 // diagonals of the real shape are prefixes of the padded ones, L^S is the leading nx x nu block.
 template <typename TF>
 __global__ void __launch_bounds__(256) k_extract_factors(const TF* __restrict__ src, TF* __restrict__ dst,
-                                                         int64_t blocks, int nx, int nu, int NX, int NU) {
-  const int64_t fr = stage_factor_elems(nx, nu), fp = stage_factor_elems(NX, NU);
-  const int64_t olr = 0, odr = (int64_t)nu * (nu + 1) / 2, ols = odr + nu, olq = ols + (int64_t)nx * nu,
-                odq = olq + (int64_t)nx * (nx + 1) / 2;
-  const int64_t Podr = (int64_t)NU * (NU + 1) / 2, Pols = Podr + NU, Polq = Pols + (int64_t)NX * NU,
-                Podq = Polq + (int64_t)NX * (NX + 1) / 2;
-  const int64_t total = blocks * fr;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t blk = e / fr, w = e - blk * fr;
-    int64_t s;
-    if (w < odr) s = olr + w;
+                                                         uint32_t blocks, int nx, int nu, int NX, int NU) {
+  const uint32_t fr = (uint32_t)stage_factor_elems(nx, nu), fp = (uint32_t)stage_factor_elems(NX, NU);
+  const uint32_t odr = nu * (nu + 1) / 2, ols = odr + nu, olq = ols + nx * nu, odq = olq + nx * (nx + 1) / 2;
+  const uint32_t Podr = NU * (NU + 1) / 2, Pols = Podr + NU, Polq = Pols + NX * NU, Podq = Polq + NX * (NX + 1) / 2;
+  const uint32_t total = blocks * fr;  // below 2^31 (the plan checks)
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const uint32_t blk = e / fr, w = e - blk * fr;
+    uint32_t s;
+    if (w < odr) s = w;
     else if (w < ols) s = Podr + (w - odr);
     else if (w < olq) {
-      const int64_t t = w - ols, i = t / nu, jj = t - i * nu;
+      const uint32_t t = w - ols, i = t / nu, jj = t - i * nu;
       s = Pols + i * NU + jj;
     } else if (w < odq) s = Polq + (w - olq);
     else s = Podq + (w - odq);
-    dst[e] = src[blk * fp + s];
+    dst[e] = src[(uint64_t)blk * fp + s];
   }
 }
 
@@ -79,6 +77,7 @@ hipError_t launch_pad(const PadOp* ops, int n, hipStream_t st) {
     all.op[i] = ops[i];
     most = std::max(most, ops[i].blocks * (ops[i].unpad ? ops[i].r : ops[i].R));
   }
+  if (most * 16 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit row indices
   const int64_t want = (most * 16 + 255) / 256;
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 4096)), (unsigned)n);
   hipLaunchKernelGGL(k_pad, grid, dim3(256), 0, st, all);
@@ -89,12 +88,13 @@ hipError_t launch_extract_small_factors(bool f64, const void* src, void* dst, in
                                         int NU, hipStream_t st) {
   const int64_t total = blocks * stage_factor_elems(nx, nu);
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192)));
+  if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   if (f64)
-    hipLaunchKernelGGL(k_extract_factors<double>, grid, dim3(256), 0, st, (const double*)src, (double*)dst, blocks,
-                       nx, nu, NX, NU);
+    hipLaunchKernelGGL(k_extract_factors<double>, grid, dim3(256), 0, st, (const double*)src, (double*)dst,
+                       (uint32_t)blocks, nx, nu, NX, NU);
   else
-    hipLaunchKernelGGL(k_extract_factors<float>, grid, dim3(256), 0, st, (const float*)src, (float*)dst, blocks, nx,
-                       nu, NX, NU);
+    hipLaunchKernelGGL(k_extract_factors<float>, grid, dim3(256), 0, st, (const float*)src, (float*)dst,
+                       (uint32_t)blocks, nx, nu, NX, NU);
   return hipGetLastError();
 }
 

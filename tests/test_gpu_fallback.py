@@ -74,6 +74,7 @@ def test_crafted_instance_fails_in_mixed_precision():
     insts = _batch()
     # the stage matrix is positive definite in exact arithmetic (and in the oracle)
     r = _run(insts, fallback=False)
+    assert r["plan"].variant == "small_padded"
     assert r["info"][2] == 3, r["info"]
     assert all(r["info"][i] == 0 for i in range(6) if i != 2), r["info"]
 
@@ -82,6 +83,9 @@ def test_fallback_recovers_the_instance():
     print("case: mixed solve with float64 fallback", flush=True)
     insts = _batch()
     r = _run(insts, fallback=True)
+    # (2, 1) has no size-specialised kernel of its own: the mixed plan runs padded to (4, 2), and the
+    # float64 subset plan addresses the parent's unpadded arrays
+    assert r["plan"].variant == "small_padded"
     assert list(r["redone"]) == [2]
     assert np.all(r["info"] == 0), r["info"]
     for i, p in enumerate(insts):

@@ -1013,6 +1013,13 @@ extern "C" int lq_qp_solve(const lq_plan* p, const lq_data* d, const lq_qp_const
         void* pitws = w + L.total;
         if ((rc = lq_pit_factor(p->batch, n0, x0, u0, P, &nd, pitws, finfo, st))) return rc;
         if ((rc = lq_pit_solve(p->batch, n0, x0, u0, P, &nd, pitws, a.dx, a.du, a.dlam, rel, finfo, st))) return rc;
+        // one refinement step with the same factors: the Schur-complement solves lose accuracy at
+        // large penalties, which would leave the inner loops with inexact directions
+        if ((e = lq::qp_refine(0, a, maxN, nxm, num, tot, st)) != hipSuccess) return launch_status(e, fn);
+        lq_data cd = nd;
+        cd.q = a.qc; cd.r = a.rc; cd.f = a.fc;
+        if ((rc = lq_pit_solve(p->batch, n0, x0, u0, P, &cd, pitws, a.cdx, a.cdu, a.cdlam, rel, finfo, st))) return rc;
+        if ((e = lq::qp_refine(1, a, maxN, nxm, num, tot, st)) != hipSuccess) return launch_status(e, fn);
       } else {
         if ((rc = lq_factor(p, &nd, pws, finfo, st))) return rc;
         if ((rc = lq_solve(p, &nd, pws, &so, a.dx, a.du, a.dlam, rel, nullptr, finfo, st))) return rc;

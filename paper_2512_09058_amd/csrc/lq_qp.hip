@@ -12,6 +12,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "lq_qp.hpp"
 
 namespace lq {
@@ -109,6 +111,76 @@ __global__ __launch_bounds__(QT) void k_qp_init(QPArgs a) {
   rollout(a, D, sm);
   for (int64_t e = tid; e < (int64_t)N * nx; e += QT) a.xbar[D.ox + e] = a.x[D.ox + e];
   for (int64_t e = tid; e < (int64_t)N * nu; e += QT) a.ubar[D.ou + e] = a.u[D.ou + e];
+}
+
+// Stage products of the refinement kernel.  Rows: one wavefront per row (four rows at a time, so
+// that their loads are in flight together), lanes over the columns, a wavefront reduction.
+// Columns: lanes over the columns, the wavefronts over the rows, partial sums through LDS.  (The
+// Newton and direction kernels keep one thread per output row: with several workgroups per CU
+// their strided reads cost less than these reductions' shuffles and barriers, measured.)
+constexpr int QW = QT / 64;  // wavefronts per workgroup
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// out(i, sum_q M[i][q] v1[q], sum_q M[i][q] v2[q]) for rows i < r of the row-major M (row length
+// ld, c columns used; v1, v2 in LDS, v2 may be null), called on lane 0 of row i's wavefront (each
+// row always on the same wavefront).
+template <typename Out>
+__device__ void rows_mv(const double* M, int r, int c, int ld, const double* v1, const double* v2, Out&& out) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i0 = 4 * w; i0 < r; i0 += 4 * QW) {
+    double s1[4], s2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      s1[t] = s2[t] = 0.0;
+      const int i = i0 + t;
+      if (i < r)
+        for (int q = lane; q < c; q += 64) {
+          const double mv = M[(int64_t)i * ld + q];
+          s1[t] = fma(mv, v1[q], s1[t]);
+          if (v2) s2[t] = fma(mv, v2[q], s2[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double a1 = wave_sum(s1[t]), a2 = v2 ? wave_sum(s2[t]) : 0.0;
+      if (lane == 0 && i0 + t < r) out(i0 + t, a1, a2);
+    }
+  }
+}
+
+// out(q, sum_i M[i][q] w1[i], sum_i M[i][q] w2[i]) for columns q < c (w1, w2 in LDS, w2 may be
+// null), called on thread q after a barrier; part: LDS of 2 QW c doubles.  Ends with a barrier.
+template <typename Out>
+__device__ void cols_mv(const double* M, int r, int c, int ld, const double* w1, const double* w2, double* part,
+                        Out&& out) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q0 = 0; q0 < c; q0 += 64) {
+    const int q = q0 + lane;
+    if (q < c) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int i = w; i < r; i += QW) {
+        const double mv = M[(int64_t)i * ld + q];
+        s1 = fma(mv, w1[i], s1);
+        if (w2) s2 = fma(mv, w2[i], s2);
+      }
+      part[w * c + q] = s1;
+      part[(QW + w) * c + q] = s2;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < c; q += QT) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < QW; ++k) {
+      s1 += part[k * c + q];
+      s2 += part[(QW + k) * c + q];
+    }
+    out(q, s1, s2);
+  }
+  __syncthreads();
 }
 
 // Newton system at the iterate, stage by stage (grid: stage groups x instances).
@@ -334,6 +406,71 @@ __global__ __launch_bounds__(QT) void k_qp_dir(QPArgs a) {
     }
     __syncthreads();
   }
+}
+
+// Refinement of a parallel-in-time Newton solve (whose Schur-complement solves lose accuracy at large
+// penalties), stage by stage: the Newton system's KKT rows (eq. opt-cond-ocp-eq with the Newton
+// Hessians, gradients qn, rn, f = 0, x_init = 0) at (dx, du, dlam), negated, as the right-hand side
+// of the correction system: r' = rn + Rn du + Sn dx + B^T lam_j, q' = qn + Sn^T du + Qn dx + A^T lam_j
+// - lam_{j-1}, f' = A dx + B du - dx_{j+1}.  Its solution added to (dx, du, dlam) cancels the residual.
+__global__ __launch_bounds__(QT) void k_qp_newton_resid(QPArgs a) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  if (a.fl[(int64_t)b * FL_N + FL_OUTER]) return;
+  const Desc D = a.desc[b];
+  const int N = D.N, nx = D.nx, nu = D.nu;
+  double* dxs = sm;        // dx_j    [nx]
+  double* dus = dxs + nx;  // du_j    [nu]
+  double* ls = dus + nu;   // lam_j   [nx]
+  double* vx = ls + nx;    // q'_j    [nx]
+  double* vu = vx + nx;    // r'_j    [nu]
+  double* vf = vu + nu;    // f'_j    [nx]
+  double* part = vf + nx;  // column partials [2 QW max(nx, nu)]
+  for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
+    for (int i = tid; i < nx; i += QT) {
+      dxs[i] = j == 0 ? 0.0 : a.dx[D.ox + (int64_t)(j - 1) * nx + i];
+      ls[i] = j < N ? a.dlam[D.olam + (int64_t)j * nx + i] : 0.0;
+      vx[i] = j >= 1 ? a.qn[D.oq + (int64_t)j * nx + i] - a.dlam[D.olam + (int64_t)(j - 1) * nx + i] : 0.0;
+      vf[i] = j < N ? -a.dx[D.ox + (int64_t)j * nx + i] : 0.0;
+    }
+    for (int c = tid; c < nu; c += QT) {
+      dus[c] = j < N ? a.du[D.ou + (int64_t)j * nu + c] : 0.0;
+      vu[c] = j < N ? a.rn[D.or_ + (int64_t)j * nu + c] : 0.0;
+    }
+    __syncthreads();
+    const double* Qn = a.Qn + D.oQ + (int64_t)j * nx * nx;
+    const double* Rn = j < N ? a.Rn + D.oR + (int64_t)j * nu * nu : nullptr;
+    const double* Sn = j < N ? a.Sn + D.oS + (int64_t)j * nu * nx : nullptr;
+    const double* Aj = j < N ? a.d.A + D.oA + (int64_t)j * nx * nx : nullptr;
+    const double* Bj = j < N ? a.d.B + D.oB + (int64_t)j * nx * nu : nullptr;
+    if (j >= 1) rows_mv(Qn, nx, nx, nx, dxs, nullptr, [&](int p, double v, double) { vx[p] += v; });
+    if (j < N) {
+      rows_mv(Rn, nu, nu, nu, dus, nullptr, [&](int c, double v, double) { vu[c] += v; });
+      rows_mv(Sn, nu, nx, nx, dxs, nullptr, [&](int c, double v, double) { vu[c] += v; });
+      rows_mv(Aj, nx, nx, nx, dxs, nullptr, [&](int p, double v, double) { vf[p] += v; });
+      rows_mv(Bj, nx, nu, nu, dus, nullptr, [&](int p, double v, double) { vf[p] += v; });
+    }
+    __syncthreads();
+    if (j < N) {
+      cols_mv(Bj, nx, nu, nu, ls, nullptr, part, [&](int c, double v, double) { vu[c] += v; });
+      if (j >= 1) {
+        cols_mv(Aj, nx, nx, nx, ls, nullptr, part, [&](int p, double v, double) { vx[p] += v; });
+        cols_mv(Sn, nu, nx, nx, dus, nullptr, part, [&](int p, double v, double) { vx[p] += v; });
+      }
+    }
+    for (int i = tid; i < nx; i += QT) {
+      a.qc[D.oq + (int64_t)j * nx + i] = vx[i];
+      if (j < N) a.fc[D.of + (int64_t)j * nx + i] = vf[i];
+    }
+    if (j < N)
+      for (int c = tid; c < nu; c += QT) a.rc[D.or_ + (int64_t)j * nu + c] = vu[c];
+    __syncthreads();
+  }
+}
+
+__global__ void k_qp_add(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] += src[i];
 }
 
 // psi'(t) = eta t + beta + sum_i delta_i [delta_i t - alpha_i]_+ (eq. psi-prime) over the rows of
@@ -669,6 +806,12 @@ QPLayout qp_layout(const int64_t* totals, int64_t sumK, int batch, int m) {
   L.odx = take(8 * totals[7]);
   L.odu = take(8 * totals[8]);
   L.odlam = take(8 * totals[9]);
+  L.oqc = take(8 * totals[3]);
+  L.orc = take(8 * totals[4]);
+  L.ofc = take(8 * totals[5]);
+  L.ocdx = take(8 * totals[7]);
+  L.ocdu = take(8 * totals[8]);
+  L.ocdlam = take(8 * totals[9]);
   L.oxb = take(8 * totals[7]);
   L.oub = take(8 * totals[8]);
   const size_t rows = 8 * (size_t)m * sumK;
@@ -700,6 +843,8 @@ QPArgs qp_args(const Desc* desc, int batch, int m, const lq_data& d, const lq_qp
   a.qn = (double*)(w + L.oqn); a.rn = (double*)(w + L.orn); a.fn = (double*)(w + L.ofn); a.x0n = (double*)(w + L.ox0n);
   a.x = x; a.u = u; a.y = y;
   a.dx = (double*)(w + L.odx); a.du = (double*)(w + L.odu); a.dlam = (double*)(w + L.odlam);
+  a.qc = (double*)(w + L.oqc); a.rc = (double*)(w + L.orc); a.fc = (double*)(w + L.ofc);
+  a.cdx = (double*)(w + L.ocdx); a.cdu = (double*)(w + L.ocdu); a.cdlam = (double*)(w + L.ocdlam);
   a.xbar = (double*)(w + L.oxb); a.ubar = (double*)(w + L.oub);
   a.sig = (double*)(w + L.osig); a.w = (double*)(w + L.ow); a.gd = (double*)(w + L.ogd);
   a.e = (double*)(w + L.oe); a.eprev = (double*)(w + L.oep);
@@ -709,7 +854,31 @@ QPArgs qp_args(const Desc* desc, int batch, int m, const lq_data& d, const lq_qp
   return a;
 }
 
-size_t qp_stage_lds(int nxmax, int numax, int m) { return sizeof(double) * (2 * (size_t)nxmax + 2 * numax + 2 * m + 8); }
+// LDS of the QP kernels: the largest is the direction kernel's (vectors and row / column sums)
+// or the Newton kernel's (with the rows' state), plus the column partials of cols_mv.
+size_t qp_stage_lds(int nxmax, int numax, int m) {
+  const size_t cm = std::max(std::max(nxmax, numax), m);
+  return sizeof(double) * (6 * (size_t)nxmax + 5 * numax + 3 * m + 2 * QW * cm + 8);
+}
+
+hipError_t qp_refine(int which, const QPArgs& a, int maxN, int nxmax, int numax, const int64_t* tot, hipStream_t st) {
+  if (which == 0) {
+    const size_t lds = qp_stage_lds(nxmax, numax, a.m);
+    const dim3 sgrid((maxN + 1 + QSG - 1) / QSG, a.batch);
+    hipError_t e = raise_lds_limit((const void*)k_qp_newton_resid, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_qp_newton_resid, sgrid, dim3(QT), lds, st, a);
+    return hipGetLastError();
+  }
+  double* dst[3] = {a.dx, a.du, a.dlam};
+  const double* src[3] = {a.cdx, a.cdu, a.cdlam};
+  const int64_t n[3] = {tot[7], tot[8], tot[9]};
+  for (int k = 0; k < 3; ++k) {
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n[k] + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_qp_add, dim3(g), dim3(256), 0, st, dst[k], src[k], n[k]);
+  }
+  return hipGetLastError();
+}
 
 hipError_t qp_launch(int which, const QPArgs& a, int maxN, int nxmax, int numax, hipStream_t st, const int32_t* info,
                      int32_t* out) {

@@ -13,6 +13,8 @@ struct QPArgs {
   double *Qn, *Rn, *Sn, *qn, *rn, *fn, *x0n;  // Newton systems (LQ data layout)
   double *x, *u, *y;             // iterate (output layout), multipliers of the rows
   double *dx, *du, *dlam;        // Newton solution (output layout)
+  double *qc, *rc, *fc;          // refinement of a parallel-in-time Newton solve: right-hand side
+  double *cdx, *cdu, *cdlam;     //   (data layout) and correction (output layout)
   double *xbar, *ubar;           // proximal centre (output layout)
   double *sig, *w, *gd, *e, *eprev;  // per row
   double *part;                  // per (instance, stage): partial sums
@@ -24,8 +26,8 @@ struct QPArgs {
 
 // Byte offsets of the QP workspace.
 struct QPLayout {
-  size_t oQn, oRn, oSn, oqn, orn, ofn, ox0n, odx, odu, odlam, oxb, oub, osig, ow, ogd, oe, oep, opart, otau,
-      ofl, orel, oinfo, ocnt, total;
+  size_t oQn, oRn, oSn, oqn, orn, ofn, ox0n, odx, odu, odlam, oqc, orc, ofc, ocdx, ocdu, ocdlam, oxb, oub, osig, ow,
+      ogd, oe, oep, opart, otau, ofl, orel, oinfo, ocnt, total;
 };
 
 // totals: elements of Q, R, S, q, r, f, x0, x, u, lam in the plan's layout; sumK = sum (N + 1).
@@ -36,6 +38,10 @@ QPArgs qp_args(const Desc* desc, int batch, int m, const lq_data& d, const lq_qp
 // 3 outer step + count of instances running (the counts go to *out).
 hipError_t qp_launch(int which, const QPArgs& a, int maxN, int nxmax, int numax, hipStream_t st, const int32_t* info,
                      int32_t* out);
+// One refinement step of a parallel-in-time Newton solve (which 0: the Newton system's KKT residual
+// at (dx, du, dlam) as the right-hand side (qc, rc, fc) of a correction system with x_init = 0;
+// which 1: (dx, du, dlam) += the correction).  tot: elements of x, u, lam (plan layout).
+hipError_t qp_refine(int which, const QPArgs& a, int maxN, int nxmax, int numax, const int64_t* tot, hipStream_t st);
 hipError_t qp_finish(const QPArgs& a, double* lam, int32_t* status, int32_t* iters, hipStream_t st);
 
 }  // namespace lq

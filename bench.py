@@ -718,6 +718,81 @@ def bench_single(args):
     print(json.dumps(out))
 
 
+def bench_shapes(args):
+    """Size-specialised shapes at the batch-4096 workload's size (4096 instances, N = 50, its
+    generators): shapes without a kernel of their own run padded to a compiled one (plan variant
+    small_padded), beside the same plans on the tile kernels and the compiled (12, 4).  Factor +
+    solve per step, HIP events; every instance's library residual; the oracle (textbook Riccati) on
+    sampled instances in the CPU leg."""
+    import torch
+    import synth
+    import paper_2512_09058_amd as L
+    from oracle import riccati
+    shapes = [(12, 4), (11, 4), (12, 3), (9, 5)]
+    res, stream = {}, torch.cuda.current_stream()
+    for nx, nu in shapes:
+        b = synth.make_batch(2, 4096, N=50, nx=nx, nu=nu)
+        data = L.pack(b)
+        for mode, mi in (("f64", 0), ("mixed_f32", args.max_it)):
+            for variant in (None, "tile"):
+                plan = L.Plan(b.N, b.nx, b.nu, batch=b.batch, mode=mode)
+                if variant:
+                    plan.set_variant(variant)
+                ws = plan.workspace()
+                info = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
+                rel = torch.zeros(plan.batch, dtype=torch.float64, device="cuda")
+                x, u, lam = plan.empty_outputs()
+                for _ in range(args.warmup):
+                    L.factor(plan, data, ws, info, stream=stream)
+                    L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=mi, stream=stream)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    L.factor(plan, data, ws, info, stream=stream)
+                    L.solve(plan, data, ws, x, u, lam, rel, None, info, tol=TOL, max_it=mi, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                key = f"{nx}x{nu}_{mode}_{plan.variant}"
+                r = {"nx": nx, "nu": nu, "mode": mode, "variant": plan.variant, "ms_per_step": ms,
+                     "solves_per_s": b.batch / (ms * 1e-3), "max_rel_res": float(rel.max().item()),
+                     "info_ok": bool((info == 0).all().item())}
+                if not args.no_cpu and variant is None and mode == "f64":
+                    errs = []
+                    for i in (0, 2047, 4095):
+                        p = b.instance(i)
+                        sol = [L.unpack(plan, n, t_, i) for n, t_ in (("x", x), ("u", u), ("lam", lam))]
+                        errs.append(_fwd_err(sol, riccati.solve(p)))
+                    r["fwd_err_vs_oracle_sampled"] = max(errs)
+                res[key] = r
+                print(f"[bench] shapes {key}: {ms:.3f} ms, max rel_res {r['max_rel_res']:.1e}", file=sys.stderr,
+                      flush=True)
+    out_cpu = None
+    if not args.no_cpu:
+        p = synth.make_batch(2, 1, N=50, nx=11, nu=4).instance(0)
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            riccati.solve(p)
+            n += 1
+        out_cpu = {"value": n / (time.perf_counter() - t0), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                   "cpu_model": cpu_model(),
+                   "sample": "one nx = 11, nu = 4, N = 50 instance solved repeatedly for 2 s by the oracle's textbook "
+                             "Riccati route in this process"}
+    head = res["11x4_f64_small_padded"]
+    out = {"metric": "LQ KKT solves/s, batch 4096 N=50, size-specialised shapes without their own kernel (padded)",
+           "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generators of the workload)",
+           "config": {"workload": "4096 x N=50, nx=11, nu=4 padded to the compiled (12, 4); also (12, 3), (9, 5), "
+                                  "the compiled (12, 4) and the tile kernels", "batch": 4096, "N": 50},
+           "shapes": res,
+           "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": "ms", "frac": None,
+                        "traffic": None},
+           "cpu_baseline": out_cpu}
+    print(json.dumps(out))
+
+
 def bench_blocktri(args):
     """Batched block-tridiagonal systems (64 systems of 64 blocks of 128: the Schur complement
     shape of a 64-interval split of the large workload): cyclic-reduction factorisation and solve,
@@ -1027,7 +1102,7 @@ def main():
     ap.add_argument("--pit-intervals", type=int, nargs="*", default=[4, 8, 16],
                     help="large workload: interval counts of the parallel-in-time path")
     ap.add_argument("--workload", choices=["batch4096", "uneven2048", "large64", "adjoint1024", "single20", "blocktri",
-                                           "update4096", "update1024x60", "qp_mass_spring"],
+                                           "update4096", "update1024x60", "qp_mass_spring", "shapes4096"],
                     default="batch4096",
                     help="measure another workload instead (its own JSON line): the 2048-instance uneven batch, "
                          "the 64-instance large-state batch, or the 1024-instance forward+adjoint batch")
@@ -1071,6 +1146,8 @@ def main():
         return bench_update(args)
     if args.workload == "qp_mass_spring":
         return bench_qp(args)
+    if args.workload == "shapes4096":
+        return bench_shapes(args)
 
     t0 = time.perf_counter()
     prob = synth.make_batch(2)

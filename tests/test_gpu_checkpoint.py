@@ -226,3 +226,30 @@ def test_tile_checkpointed_wide_state_and_bf16(mode, max_it):
         assert kkt.residual(b.instance(i), *sol)[1] <= 1e-10, i
         assert forward_error(sol, oracle_solution(b.instance(i))) <= 1e-9, i
         assert forward_error(sol, instance_solution(full, i)) <= bar, i
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed_bf16"])
+def test_tile_checkpointed_adjoint_wide_state(mode):
+    """Gradients through the checkpointed tile path at padded nx 128 (nx = 100, nu = 20), float64
+    and bf16 products: against the same plan without checkpoints and the oracle's dense adjoint."""
+    from oracle import adjoint
+    print(f"case: tile checkpointed adjoint nx=100 {mode}", flush=True)
+    b = synth.make_batch(4, batch=2, N=12, nx=100, nu=20)
+    grads = []
+    for ckpt in (0, 5):
+        t = {k: torch.tensor(getattr(b, k), dtype=torch.float64, device="cuda", requires_grad=True)
+             for k in ("A", "B", "Q", "R", "q", "r", "x0")}
+        x, u, _ = lq_solve(t["A"], t["B"], t["Q"], t["R"], t["q"], t["r"], t["x0"], mode=mode, ckpt_stride=ckpt,
+                           variant="tile", max_it=12)
+        (0.5 * (x.pow(2).sum() + u.pow(2).sum())).backward()
+        grads.append({k: v.grad.clone() for k, v in t.items()})
+    for i in range(b.batch):
+        p = b.instance(i)
+        xo, uo, _ = kkt.solve_dense(p)
+        _, gx, gu = adjoint.quad_loss(xo, uo)
+        ref, _, _ = adjoint.adjoint_grad(p, gx, gu)
+        for k in grads[0]:
+            g0, g1 = grads[0][k][i].cpu().numpy(), grads[1][k][i].cpu().numpy()
+            scale = max(1.0, np.abs(ref[k]).max())
+            assert np.abs(g1 - g0).max() <= 1e-9 * scale, (i, k)
+            assert np.abs(g1 - ref[k]).max() <= 1e-7 * scale, (i, k)

@@ -163,9 +163,14 @@ __device__ __forceinline__ typename MM<TP>::V tmm(typename MM<TP>::V acc, const 
 // trailing updates, so the next pivot's chain overlaps them.
 // 1 / sqrt(d): the hardware estimate y (about 5e-8 relative) with one third-order correction,
 // y (1 + e / 2 + 3 e^2 / 8), e = 1 - d y^2 (error O(e^3), so rounding-limited), folded into the
-// products that use it; the column is broadcast from before the diagonal lane's select, which
-// keeps the per-pivot dependency chain at about ten instructions.
-__device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c, int n) {
+// products that use it; the column is broadcast from before the diagonal lane's select, and the
+// failure handling stays off the chain (a second pass, see chol16_pass), which keeps the
+// per-pivot dependency chain at about eight instructions.
+// SAFE = false: the pivot chain without the failure handling (a pivot that is not positive and
+// finite leaves non-finite entries, and the caller factors the tile again with SAFE = true, which
+// replaces it by 1); the returned classification is the same in both.
+template <bool SAFE>
+__device__ __forceinline__ int chol16_pass(double (&h)[16], double& dinv, int c, int n) {
   // the first failing pivot classifies the tile (see the comment above)
   int kind = 0;
   dinv = 1.0;  // rows of skipped padding pivots keep it
@@ -177,18 +182,27 @@ __device__ __forceinline__ int chol16(double (&h)[16], double& dinv, int c, int 
       for (int j = j0; j < j0 + 4; ++j) {
         const bool good = dj > 0.0 && dj <= 1.7976931348623157e308;
         kind = kind ? kind : (good ? 0 : (isfinite(dj) ? 1 : 2));
+        // x (1 + e p) with e = 1 - dj y^2, p = 1/2 + 3 e / 8, as fma(x e, p, x)
         const double t = dj * y;
         const double e = fma(-t, y, 1.0);
-        const double corr = e * fma(e, 0.375, 0.5);
+        const double pp = fma(e, 0.375, 0.5);
         const double hy = h[j] * y;
         // column j of L below the pivot (a failed pivot counts as 1: the column is kept)
-        const double hs = good ? fma(hy, corr, hy) : h[j];
-        const double dg = good ? fma(t, corr, t) : 1.0, di = good ? fma(y, corr, y) : 1.0;
+        double hs = fma(hy * e, pp, hy);
+        double dg = fma(t * e, pp, t), di = fma(y * e, pp, y);
+        if (SAFE) {
+          hs = good ? hs : h[j];
+          dg = good ? dg : 1.0;
+          di = good ? di : 1.0;
+        }
         // look-ahead: the next pivot's column first, and its 1/sqrt estimate, then the other
-        // updates, which issue while that estimate is in flight
+        // updates, which issue while that estimate is in flight.  The next pivot is lane j+1's
+        // updated entry fma(-L[j+1][j], L[j+1][j], h[j+1]), formed on every lane from the two
+        // broadcasts (the same operands, so the same value) instead of broadcast after the update.
         if (j + 1 < 16) {
-          h[j + 1] = fma(-hs, bc(hs, j + 1), h[j + 1]);
-          dj = bc(h[j + 1], j + 1);
+          const double b = bc(hs, j + 1), hold = bc(h[j + 1], j + 1);
+          h[j + 1] = fma(-hs, b, h[j + 1]);
+          dj = fma(-b, b, hold);
           y = __builtin_amdgcn_rsq(dj);
         }
 #pragma unroll
@@ -576,7 +590,14 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           double h[16];
 #pragma unroll
           for (int q = 0; q < 16; ++q) h[q] = SC[c * LD + q];
-          const int bad = chol16(h, dinv, c, nreal);
+          int bad = chol16_pass<false>(h, dinv, c, nreal);
+          if (__builtin_amdgcn_readfirstlane(bad) != 0) {
+            // a pivot failed (the classification is the same on every lane): again from the
+            // staged tile, with failed pivots replaced by 1
+#pragma unroll
+            for (int q = 0; q < 16; ++q) h[q] = SC[c * LD + q];
+            bad = chol16_pass<true>(h, dinv, c, nreal);
+          }
           if (bad && lane == 0 && s_info == 0) s_info = bad == 2 ? LQ_INFO_NONFINITE : k + 1;
           // U(j, j) = L_jj^T into its panel / the L^Q tiles
 #pragma unroll

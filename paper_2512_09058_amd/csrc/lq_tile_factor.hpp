@@ -451,13 +451,14 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
 #pragma unroll
       for (int bb = 0; bb < TMAX; ++bb) Gs[bb] = PV{0, 0, 0, 0};
       double part = 0.0;
-      for (int m = 0; m < TX; ++m) {
+      // one slab, with the C fragments of tiles m and m + 1 read by the caller (as a function of
+      // its own the slab step compiles to a tighter schedule at ten tile columns: large workload
+      // factor 110.7 -> 103.8 ms, measured)
+      auto slab = [&](int m, d4 cur, d4 nxt) {
         PV Wf = PV{0, 0, 0, 0};
         if (own) {
           // unrolled, with an exit instead of a guarded body, so that the fragments in flight
           // rotate by renaming: a register copy of a fragment would wait for its load
-          d4 cur = load_c(m);
-          d4 nxt = load_c(min(m + 1, TX - 1));
 #pragma unroll
           for (int q = 0; q < TMAX - 1; ++q) {
             const int mp = m + q;
@@ -484,7 +485,8 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
           for (int bb = 0; bb < TMAX; ++bb)
             if (bb <= a && (k > 0 || bb < TU)) Gs[bb] = tmm<TP, true>(Gs[bb], wsl(m, bb), LW, Wf, g, c);
         }
-      }
+      };
+      for (int m = 0; m < TX; ++m) slab(m, load_c(m), load_c(min(m + 1, TX - 1)));
       __syncthreads();
       if (rhs && own) {
         part += __shfl_xor(part, 16);

@@ -784,8 +784,8 @@ def bench_shapes(args):
            "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generators of the workload)",
-           "config": {"workload": "4096 x N=50, nx=11, nu=4 padded to the compiled (12, 4); also (12, 3), (9, 5), "
-                                  "the compiled (12, 4) and the tile kernels", "batch": 4096, "N": 50},
+           "config": {"workload": "4096 x N=50, nx=11, nu=4 padded to the compiled (11, 5); also (12, 3) padded "
+                                  "to (12, 4), (9, 5) padded to (9, 7), the compiled (12, 4) and the tile kernels", "batch": 4096, "N": 50},
            "shapes": res,
            "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": "ms", "frac": None,
                         "traffic": None},

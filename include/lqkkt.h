@@ -101,7 +101,9 @@ typedef struct {
 typedef struct {
   double tol;      /* target for rel_res = ||b - K z||_inf / ||b||_inf (e.g. 1e-10)              */
   int32_t max_it;  /* maximum refinement iterations (>= 0); in LQ_F64 mode 0 is usual            */
-  int32_t check;   /* 1: compute the float64 KKT residual of the final iterate into rel_res      */
+  int32_t check;   /* 1: compute the float64 KKT residual of the final iterate into rel_res;     */
+                   /* with 0 and max_it == 0 no residual is formed: rel_res (if given) reads NaN */
+                   /* and info keeps the factor's code (a non-finite solve goes unreported)     */
 } lq_solve_opts;
 
 /* Opaque plan: sizes of every instance, precision, kernel variant, descriptor table. */

@@ -1000,7 +1000,9 @@ extern "C" int lq_qp_solve(const lq_plan* p, const lq_data* d, const lq_qp_const
   double* rel = (double*)(w + L.orel);
   int32_t* cnt = (int32_t*)(w + L.ocnt);
   lq_data nd = *d;
-  nd.Q = a.Qn; nd.R = a.Rn; nd.S = a.Sn; nd.q = a.qn; nd.r = a.rn; nd.f = a.fn; nd.x0 = a.x0n;
+  // the iterate is a rollout of the dynamics, so the Newton systems' dynamics right-hand side is
+  // zero (f absent)
+  nd.Q = a.Qn; nd.R = a.Rn; nd.S = a.Sn; nd.q = a.qn; nd.r = a.rn; nd.f = nullptr; nd.x0 = a.x0n;
   const lq_solve_opts so = {1e-10, 0, 0};
   const int maxN = p->maxN, nxm = p->maxnx, num = p->maxnu;
   hipError_t e = lq::qp_launch(0, a, maxN, nxm, num, st, nullptr, nullptr);

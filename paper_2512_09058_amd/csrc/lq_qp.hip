@@ -103,7 +103,6 @@ __global__ __launch_bounds__(QT) void k_qp_init(QPArgs a) {
     a.sig[oR + e] = a.sigma0;
     a.eprev[oR + e] = INFINITY;
   }
-  for (int64_t e = tid; e < (int64_t)N * nx; e += QT) a.fn[D.of + e] = 0.0;
   for (int i = tid; i < nx; i += QT) a.x0n[D.ox0 + i] = 0.0;
   if (tid < FL_N) a.fl[(int64_t)b * FL_N + tid] = 0;
   if (tid == 0) a.tau[b] = 0.0;
@@ -801,7 +800,6 @@ QPLayout qp_layout(const int64_t* totals, int64_t sumK, int batch, int m) {
   L.oSn = take(8 * totals[2]);
   L.oqn = take(8 * totals[3]);
   L.orn = take(8 * totals[4]);
-  L.ofn = take(8 * totals[5]);
   L.ox0n = take(8 * totals[6]);
   L.odx = take(8 * totals[7]);
   L.odu = take(8 * totals[8]);
@@ -840,7 +838,7 @@ QPArgs qp_args(const Desc* desc, int batch, int m, const lq_data& d, const lq_qp
   a.d = d;
   a.C = c.C; a.D = c.D; a.bl = c.bl; a.bu = c.bu;
   a.Qn = (double*)(w + L.oQn); a.Rn = (double*)(w + L.oRn); a.Sn = (double*)(w + L.oSn);
-  a.qn = (double*)(w + L.oqn); a.rn = (double*)(w + L.orn); a.fn = (double*)(w + L.ofn); a.x0n = (double*)(w + L.ox0n);
+  a.qn = (double*)(w + L.oqn); a.rn = (double*)(w + L.orn); a.x0n = (double*)(w + L.ox0n);
   a.x = x; a.u = u; a.y = y;
   a.dx = (double*)(w + L.odx); a.du = (double*)(w + L.odu); a.dlam = (double*)(w + L.odlam);
   a.qc = (double*)(w + L.oqc); a.rc = (double*)(w + L.orc); a.fc = (double*)(w + L.ofc);

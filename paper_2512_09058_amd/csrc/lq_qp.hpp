@@ -10,7 +10,7 @@ struct QPArgs {
   int32_t batch, m;
   lq_data d;                     // the problem (cost and dynamics)
   const double *C, *D, *bl, *bu;  // constraint rows
-  double *Qn, *Rn, *Sn, *qn, *rn, *fn, *x0n;  // Newton systems (LQ data layout)
+  double *Qn, *Rn, *Sn, *qn, *rn, *x0n;  // Newton systems (LQ data layout; no f: they have f = 0)
   double *x, *u, *y;             // iterate (output layout), multipliers of the rows
   double *dx, *du, *dlam;        // Newton solution (output layout)
   double *qc, *rc, *fc;          // refinement of a parallel-in-time Newton solve: right-hand side
@@ -26,7 +26,7 @@ struct QPArgs {
 
 // Byte offsets of the QP workspace.
 struct QPLayout {
-  size_t oQn, oRn, oSn, oqn, orn, ofn, ox0n, odx, odu, odlam, oqc, orc, ofc, ocdx, ocdu, ocdlam, oxb, oub, osig, ow,
+  size_t oQn, oRn, oSn, oqn, orn, ox0n, odx, odu, odlam, oqc, orc, ofc, ocdx, ocdu, ocdlam, oxb, oub, osig, ow,
       ogd, oe, oep, opart, otau, ofl, orel, oinfo, ocnt, total;
 };
 

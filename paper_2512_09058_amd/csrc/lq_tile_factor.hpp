@@ -403,18 +403,29 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
       // ---- w = L^Q_{k+1} (L^Q_{k+1})^T f_k + p_{k+1}
       if (!rhs) {
       } else if (fg) {
+        // t1 = (L^Q_{k+1})^T f_k, then w = L^Q_{k+1} t1 + p_{k+1}: every entry is summed by four
+        // neighbouring lanes (every fourth term each, so that the serial chains are a quarter as
+        // long) and combined by two shuffles; the trip count of the outer loop is uniform
         const double* fk = fg + (int64_t)k * nx;
-        for (int j = tid; j < nx; j += nt) {
+        const int sl = tid & 3;
+        for (int e0 = 0; e0 < 16 * TX; e0 += nt >> 2) {
+          const int e = e0 + (tid >> 2);
           double s = 0.0;
-          for (int i = j; i < nx; ++i) s += (double)lqb(j >> 4, i >> 4)[(j & 15) * LQ + (i & 15)] * fk[i];
-          t1[j] = s;
+          if (e < nx)
+            for (int i = e + sl; i < nx; i += 4) s = fma((double)lqb(e >> 4, i >> 4)[(e & 15) * LQ + (i & 15)], fk[i], s);
+          s += __shfl_xor(s, 1);
+          s += __shfl_xor(s, 2);
+          if (sl == 0 && e < nx) t1[e] = s;
         }
         __syncthreads();
-        for (int i = tid; i < 16 * TX; i += nt) {
-          double s = pv[i];
-          if (i < nx)
-            for (int j = 0; j <= i; ++j) s += (double)lqb(j >> 4, i >> 4)[(j & 15) * LQ + (i & 15)] * t1[j];
-          wv[i] = s;
+        for (int e0 = 0; e0 < 16 * TX; e0 += nt >> 2) {
+          const int e = e0 + (tid >> 2);
+          double s = 0.0;
+          if (e < nx)
+            for (int j = sl; j <= e; j += 4) s = fma((double)lqb(j >> 4, e >> 4)[(j & 15) * LQ + (e & 15)], t1[j], s);
+          s += __shfl_xor(s, 1);
+          s += __shfl_xor(s, 2);
+          if (sl == 0 && e < 16 * TX) wv[e] = pv[e] + s;
         }
       } else {
         for (int i = tid; i < 16 * TX; i += nt) wv[i] = pv[i];

@@ -443,9 +443,11 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
   // vectors (nt >= NXP >= nx, nu).
   const bool rx = tid < nx, ru = tid < nu;
 
-  // ---- forward rollout (mode 0: z = result, mode 1: z += correction) with the residual of the
-  // updated iterate: correction right-hand sides for a following backward pass, returns rel_res.
-  auto forward = [&](int mode, const double* rbv, const double* pvv) -> double {
+  // ---- forward rollout (mode 0: z = result, mode 1: z += correction) with, when `res`, the
+  // residual of the updated iterate: correction right-hand sides for a following backward pass,
+  // returns rel_res (NaN without `res`, which only a first pass with no refinement and no
+  // certificate asked for takes).
+  auto forward = [&](int mode, const double* rbv, const double* pvv, bool res) -> double {
     double mr = 0.0, mb = 0.0;
     if (rx) {
       xc[tid] = mode == 0 ? rhs_x0(tid) : 0.0;
@@ -464,7 +466,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       // vectors, the other stage matrices into registers and the triangles into LDS
       Frag<(NXP <= 64 ? S::RXX : 1), S::XC, S::XW> fQ;
       if constexpr (NXP <= 64) {
-        if (k > 0) frag_load<ORD>(fQ, Qk, nx, nx, nx, L, W);
+        if (res && k > 0) frag_load<ORD>(fQ, Qk, nx, nx, nx, L, W);
       }
       // vectors: unconditional loads from clamped indices (entries past nx / nu are never used)
       const int iu = ru ? tid : nu - 1, ix = rx ? tid : nx - 1;
@@ -485,15 +487,15 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       frag_load<ORD>(fLS, blk + off_LS(nx, nu), nx, nu, nu, L, W);
       frag_load<ORD>(fA, Ak, nx, nx, nx, L, W);
       frag_load<ORD>(fB, Bk, nx, nu, nu, L, W);
-      frag_load<ORD>(fR, R + (int64_t)k * nu * nu, nu, nu, nu, L, W);
-      if (Sm) frag_load<ORD>(fS, Sm + (int64_t)k * nu * nx, nu, nx, nx, L, W);
+      if (res) frag_load<ORD>(fR, R + (int64_t)k * nu * nu, nu, nu, nu, L, W);
+      if (res && Sm) frag_load<ORD>(fS, Sm + (int64_t)k * nu * nx, nu, nx, nx, L, W);
       tri_to_lds<S::NT, tri_chunk(NUP, S::NT)>(blk, nu, LR);
       if constexpr (!LQREG) tri_to_lds<S::NT, tri_chunk(NXP, S::NT)>(blk1 + off_LQ(nx, nu), nx, LQ);
       // Q_k x_k (rows, into xs) and Q_k^T x_k (columns, hq) of the total iterate, k >= 1
       double hq[S::XC];
 #pragma unroll
       for (int c = 0; c < S::XC; ++c) hq[c] = 0.0;
-      if (k > 0) {
+      if (res && k > 0) {
         if constexpr (NXP <= 64) {
           frag_rows(fQ, xt, nx, L, W, [&](int i, double v) { xs[i] = v; });
           frag_cols(fQ, xt, nx, hq, L, W);
@@ -532,7 +534,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       // x_{k+1} = A x_k + B u_k + f_k (chain); A x_k + B u_k of the total iterate (residual)
       frag_rows(fA, xc, nx, L, W, [&](int i, double v) { xn[i] += v; });
       if (mode != 0) frag_rows(fA, xt, nx, L, W, [&](int i, double v) { al[i] = v; });
-      if (k == 0) frag_rows(fA, xt, nx, L, W, [&](int i, double v) { a0[i] = v; });
+      if (res && k == 0) frag_rows(fA, xt, nx, L, W, [&](int i, double v) { a0[i] = v; });
       __syncthreads();
       frag_rows(fB, uu, nx, L, W, [&](int i, double v) { xn[i] += v; });
       __syncthreads();
@@ -570,49 +572,51 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       }
       __syncthreads();
       // residual rows of stage k (total iterate)
-      {
-        double cx[S::XC];
+      if (res) {
+        {
+          double cx[S::XC];
 #pragma unroll
-        for (int c = 0; c < S::XC; ++c) cx[c] = 0.0;
-        double cu[1] = {0.0};
-        frag_cols(fA, lt, nx, cx, L, W);      // A^T lam_k
-        frag_cols(fB, lt, nx, cu, L, W);      // B^T lam_k
-        if (k > 0) {
+          for (int c = 0; c < S::XC; ++c) cx[c] = 0.0;
+          double cu[1] = {0.0};
+          frag_cols(fA, lt, nx, cx, L, W);      // A^T lam_k
+          frag_cols(fB, lt, nx, cu, L, W);      // B^T lam_k
+          if (k > 0) {
 #pragma unroll
-          for (int c = 0; c < S::XC; ++c) cx[c] = fma(0.5, hq[c], cx[c]);
+            for (int c = 0; c < S::XC; ++c) cx[c] = fma(0.5, hq[c], cx[c]);
+          }
+          double hr[1] = {0.0};
+          frag_cols(fR, ut, nu, hr, L, W);      // R^T u_k
+          cu[0] = fma(0.5, hr[0], cu[0]);
+          if (Sm) frag_cols(fS, ut, nu, cx, L, W);  // S^T u_k
+          colsum_publish<S::XC, S::XW>(cx, px, NXP, L);
+          colsum_publish<1, S::UW>(cu, pu, NUP, L);
         }
-        double hr[1] = {0.0};
-        frag_cols(fR, ut, nu, hr, L, W);      // R^T u_k
-        cu[0] = fma(0.5, hr[0], cu[0]);
-        if (Sm) frag_cols(fS, ut, nu, cx, L, W);  // S^T u_k
-        colsum_publish<S::XC, S::XW>(cx, px, NXP, L);
-        colsum_publish<1, S::UW>(cu, pu, NUP, L);
-      }
-      __syncthreads();
-      if (rx) ax[tid] = colsum_total(px, NXP, W, tid) + (k > 0 ? 0.5 * xs[tid] : 0.0);
-      if (ru) au[tid] = colsum_total(pu, NUP, W, tid);
-      __syncthreads();
-      frag_rows(fR, ut, nu, L, W, [&](int i, double v) { au[i] = fma(0.5, v, au[i]); });
-      __syncthreads();
-      if (Sm) frag_rows(fS, xt, nu, L, W, [&](int i, double v) { au[i] += v; if (k == 0) s0[i] = v; });
-      __syncthreads();
-      if (ru) {
-        const double rho = -v_r - au[tid];
-        mr = nan_max(mr, fabs(rho));
-        mb = nan_max(mb, fabs(v_r + (k == 0 && Sm ? s0[tid] : 0.0)));
-        rhu[(int64_t)k * nu + tid] = -rho;
-      }
-      if (rx) {
-        const double axu = mode == 0 ? xn[tid] - v_f : al[tid];
-        const double rho = -v_f - (axu - xt1[tid]);
-        mr = nan_max(mr, fabs(rho));
-        mb = nan_max(mb, fabs(v_f + (k == 0 ? a0[tid] : 0.0)));
-        flam[(int64_t)k * nx + tid] = -rho;
-        if (k > 0) {
-          const double rho2 = -v_q - (ax[tid] - ltm[tid]);
-          mr = nan_max(mr, fabs(rho2));
-          mb = nan_max(mb, fabs(v_q));
-          rhx[(int64_t)k * nx + tid] = -rho2;
+        __syncthreads();
+        if (rx) ax[tid] = colsum_total(px, NXP, W, tid) + (k > 0 ? 0.5 * xs[tid] : 0.0);
+        if (ru) au[tid] = colsum_total(pu, NUP, W, tid);
+        __syncthreads();
+        frag_rows(fR, ut, nu, L, W, [&](int i, double v) { au[i] = fma(0.5, v, au[i]); });
+        __syncthreads();
+        if (Sm) frag_rows(fS, xt, nu, L, W, [&](int i, double v) { au[i] += v; if (k == 0) s0[i] = v; });
+        __syncthreads();
+        if (ru) {
+          const double rho = -v_r - au[tid];
+          mr = nan_max(mr, fabs(rho));
+          mb = nan_max(mb, fabs(v_r + (k == 0 && Sm ? s0[tid] : 0.0)));
+          rhu[(int64_t)k * nu + tid] = -rho;
+        }
+        if (rx) {
+          const double axu = mode == 0 ? xn[tid] - v_f : al[tid];
+          const double rho = -v_f - (axu - xt1[tid]);
+          mr = nan_max(mr, fabs(rho));
+          mb = nan_max(mb, fabs(v_f + (k == 0 ? a0[tid] : 0.0)));
+          flam[(int64_t)k * nx + tid] = -rho;
+          if (k > 0) {
+            const double rho2 = -v_q - (ax[tid] - ltm[tid]);
+            mr = nan_max(mr, fabs(rho2));
+            mb = nan_max(mb, fabs(v_q));
+            rhx[(int64_t)k * nx + tid] = -rho2;
+          }
         }
       }
       __syncthreads();
@@ -623,6 +627,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       }
       __syncthreads();
     }
+    if (!res) return (double)NAN;
     // stage N rows: rho_x,N = -q_N - (Q_N,sym x_N - lam_{N-1})
     {
       const Lanes L = lanes_now();
@@ -769,7 +774,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
     const bool first = it < 0;
     if (!first || adj) backward();
     const bool f0 = first && !adj;
-    rel = forward(f0 ? 0 : 1, f0 ? rb0 : rb2, f0 ? p0 : p2);
+    rel = forward(f0 ? 0 : 1, f0 ? rb0 : rb2, f0 ? p0 : p2, want || !f0);
     ++it;
     if (!(want && rel > a.tol && it < a.max_it)) break;
   }
@@ -780,7 +785,7 @@ __device__ __forceinline__ void tsolve_one(const SolveArgs& a, int b, double* sm
       const int cur = a.info[b];
       if (cur <= 0) {
         int code = 0;
-        if (!isfinite(rel)) code = LQ_INFO_NONFINITE;
+        if (want && !isfinite(rel)) code = LQ_INFO_NONFINITE;
         else if (a.max_it > 0 && rel > a.tol) code = LQ_INFO_NOT_CONVERGED;
         else if (cur == LQ_INFO_NONFINITE) code = cur;
         a.info[b] = code;

@@ -120,6 +120,28 @@ def test_tile_indefinite_and_nonfinite_report_info():
     assert res["info"][2] == 0
 
 
+@pytest.mark.parametrize("variant,ckpt", [("tile", 0), ("tile", 2), ("generic", 0)])
+def test_solve_without_certificate(variant, ckpt):
+    """opts.check = 0 with max_it = 0: the residual is not formed, rel_res reads NaN, info stays 0,
+    and x, u, lam are the certified solve's bit for bit (stored and checkpointed tile factors, and
+    the generic kernels, which skipped it already)."""
+    insts = [_well_conditioned(640 + i, 9, 24, 6) for i in range(3)]
+    out = []
+    for check in (True, False):
+        print(f"case: {variant} ckpt={ckpt} check={check}", flush=True)
+        plan = L.Plan([p.N for p in insts], [p.nx for p in insts], [p.nu for p in insts], mode="f64",
+                      ckpt_stride=ckpt)
+        plan.set_variant(variant)
+        out.append(run(insts, "f64", max_it=0, check=check, plan=plan))
+    on, off = out
+    assert np.all(on["info"] == 0) and np.all(off["info"] == 0), (on["info"], off["info"])
+    assert on["rel"].max() <= 1e-10 and np.all(np.isnan(off["rel"])), (on["rel"], off["rel"])
+    for key in ("x", "u", "lam"):
+        assert on[key].cpu().numpy().tobytes() == off[key].cpu().numpy().tobytes(), key
+    for i in range(len(insts)):
+        assert forward_error(instance_solution(off, i), oracle_solution(insts[i])) <= 1e-9, i
+
+
 def test_tile_adjoint_consumes_tile_factors():
     """lq_solve_backward on tile factors: gradients vs the oracle's dense adjoint."""
     from oracle import adjoint

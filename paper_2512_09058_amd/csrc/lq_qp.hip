@@ -183,6 +183,15 @@ __device__ void cols_mv(const double* M, int r, int c, int ld, const double* w1,
 }
 
 // Newton system at the iterate, stage by stage (grid: stage groups x instances).
+// Stage-parallel kernels: with STG the stage's matrices are first copied into LDS (one coalesced
+// pass, every load in flight at once), so that the per-row loops below read LDS instead of
+// waiting on one global load after another; the arithmetic, and its order, is the same either way.
+// Copy n doubles from global memory into LDS with the whole workgroup.
+__device__ __forceinline__ void stage_copy(double* dst, const double* __restrict__ src, int n) {
+  for (int e = threadIdx.x; e < n; e += QT) dst[e] = src[e];
+}
+
+template <bool STG>
 __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
   extern __shared__ double sm[];
   __shared__ double red[QT / 64];
@@ -200,16 +209,39 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
     const double* xj = j == 0 ? a.d.x0 + D.ox0 : a.x + D.ox + (int64_t)(j - 1) * nx;
     for (int i = tid; i < nx; i += QT) xs[i] = xj[i];
     for (int c = tid; c < nu; c += QT) us[c] = j < N ? a.u[D.ou + (int64_t)j * nu + c] : 0.0;
-    __syncthreads();
+    // stage matrices (Dj, Rj, Sj null where the stage has none; the staged copies are read only
+    // where the global ones are not null)
     const double* Cj = a.C + (int64_t)m * D.oq + (int64_t)j * m * nx;
     const double* Dj = j < N ? a.D + (int64_t)m * D.or_ + (int64_t)j * m * nu : nullptr;
+    const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
+    const double* Rj = j < N ? a.d.R + D.oR + (int64_t)j * nu * nu : nullptr;
+    const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
+    const double *Cs = Cj, *Ds = Dj, *Qs = Qj, *Rs = Rj, *Ss = Sj;
+    if constexpr (STG) {
+      double* p = sm + a.omats;
+      stage_copy(p, Cj, m * nx);
+      Cs = p;
+      p += m * nx;
+      if (Dj) stage_copy(p, Dj, m * nu);
+      Ds = p;
+      p += m * nu;
+      stage_copy(p, Qj, nx * nx);
+      Qs = p;
+      p += nx * nx;
+      if (Rj) stage_copy(p, Rj, nu * nu);
+      Rs = p;
+      p += nu * nu;
+      if (Sj) stage_copy(p, Sj, nu * nx);
+      Ss = p;
+    }
+    __syncthreads();
     const int64_t rj = (int64_t)m * D.oK + (int64_t)j * m;
     double sc = 0.0;
     for (int i = tid; i < m; i += QT) {
       double wi = 0.0;
-      for (int c = 0; c < nx; ++c) wi += Cj[(int64_t)i * nx + c] * xs[c];
+      for (int c = 0; c < nx; ++c) wi += Cs[(int64_t)i * nx + c] * xs[c];
       if (Dj)
-        for (int c = 0; c < nu; ++c) wi += Dj[(int64_t)i * nu + c] * us[c];
+        for (int c = 0; c < nu; ++c) wi += Ds[(int64_t)i * nu + c] * us[c];
       const double s = a.sig[rj + i], yi = a.y[rj + i];
       const double v = wi + yi / s;
       const double lo = a.bl[rj + i], hi = a.bu[rj + i];
@@ -234,37 +266,34 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
     __syncthreads();
     const int na = s_na;
     // Hessian blocks
-    const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
     double* Qnj = a.Qn + D.oQ + (int64_t)j * nx * nx;
     for (int e = tid; e < nx * nx; e += QT) {
       const int p = e / nx, q = e % nx;
-      double h = 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]) + (p == q ? a.ginv : 0.0);
+      double h = 0.5 * (Qs[p * nx + q] + Qs[q * nx + p]) + (p == q ? a.ginv : 0.0);
       for (int t = 0; t < na; ++t) {
         const int i = s_act[t];
-        h += ss[i] * Cj[(int64_t)i * nx + p] * Cj[(int64_t)i * nx + q];
+        h += ss[i] * Cs[(int64_t)i * nx + p] * Cs[(int64_t)i * nx + q];
       }
       Qnj[e] = h;
     }
-    const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
     if (j < N) {
-      const double* Rj = a.d.R + D.oR + (int64_t)j * nu * nu;
       double* Rnj = a.Rn + D.oR + (int64_t)j * nu * nu;
       for (int e = tid; e < nu * nu; e += QT) {
         const int p = e / nu, q = e % nu;
-        double h = 0.5 * (Rj[p * nu + q] + Rj[q * nu + p]) + (p == q ? a.ginv : 0.0);
+        double h = 0.5 * (Rs[p * nu + q] + Rs[q * nu + p]) + (p == q ? a.ginv : 0.0);
         for (int t = 0; t < na; ++t) {
           const int i = s_act[t];
-          h += ss[i] * Dj[(int64_t)i * nu + p] * Dj[(int64_t)i * nu + q];
+          h += ss[i] * Ds[(int64_t)i * nu + p] * Ds[(int64_t)i * nu + q];
         }
         Rnj[e] = h;
       }
       double* Snj = a.Sn + D.oS + (int64_t)j * nu * nx;
       for (int e = tid; e < nu * nx; e += QT) {
         const int p = e / nx, q = e % nx;
-        double h = Sj ? Sj[e] : 0.0;
+        double h = Sj ? Ss[e] : 0.0;
         for (int t = 0; t < na; ++t) {
           const int i = s_act[t];
-          h += ss[i] * Dj[(int64_t)i * nu + p] * Cj[(int64_t)i * nx + q];
+          h += ss[i] * Ds[(int64_t)i * nu + p] * Cs[(int64_t)i * nx + q];
         }
         Snj[e] = h;
       }
@@ -272,10 +301,10 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
       const double* ubj = a.ubar + D.ou + (int64_t)j * nu;
       for (int c = tid; c < nu; c += QT) {
         double g = a.d.r[D.or_ + (int64_t)j * nu + c] + a.ginv * (us[c] - ubj[c]);
-        for (int q = 0; q < nu; ++q) g += 0.5 * (Rj[c * nu + q] + Rj[q * nu + c]) * us[q];
+        for (int q = 0; q < nu; ++q) g += 0.5 * (Rs[c * nu + q] + Rs[q * nu + c]) * us[q];
         if (Sj)
-          for (int q = 0; q < nx; ++q) g += Sj[(int64_t)c * nx + q] * xs[q];
-        for (int t = 0; t < na; ++t) g += Dj[(int64_t)s_act[t] * nu + c] * yh[s_act[t]];
+          for (int q = 0; q < nx; ++q) g += Ss[(int64_t)c * nx + q] * xs[q];
+        for (int t = 0; t < na; ++t) g += Ds[(int64_t)s_act[t] * nu + c] * yh[s_act[t]];
         a.rn[D.or_ + (int64_t)j * nu + c] = g;
       }
     }
@@ -283,10 +312,10 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
     const double* xbj = j >= 1 ? a.xbar + D.ox + (int64_t)(j - 1) * nx : nullptr;
     for (int p = tid; p < nx; p += QT) {
       double g = a.d.q[D.oq + (int64_t)j * nx + p] + (xbj ? a.ginv * (xs[p] - xbj[p]) : 0.0);
-      for (int q = 0; q < nx; ++q) g += 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]) * xs[q];
+      for (int q = 0; q < nx; ++q) g += 0.5 * (Qs[p * nx + q] + Qs[q * nx + p]) * xs[q];
       if (Sj)
-        for (int c = 0; c < nu; ++c) g += Sj[(int64_t)c * nx + p] * us[c];
-      for (int t = 0; t < na; ++t) g += Cj[(int64_t)s_act[t] * nx + p] * yh[s_act[t]];
+        for (int c = 0; c < nu; ++c) g += Ss[(int64_t)c * nx + p] * us[c];
+      for (int t = 0; t < na; ++t) g += Cs[(int64_t)s_act[t] * nx + p] * yh[s_act[t]];
       a.qn[D.oq + (int64_t)j * nx + p] = g;
     }
     __syncthreads();
@@ -307,6 +336,7 @@ __global__ void k_qp_check_info(QPArgs a, const int32_t* info) {
 // Direction measures, stage by stage: G d per row, the stage parts of eta and beta (eq. psi-prime:
 // the cost's quadratic form and gradient along d, with the proximal term), the inner stationarity
 // residual grad + M^T lam with the Newton multipliers, and |d|.
+template <bool STG>
 __global__ __launch_bounds__(QT) void k_qp_dir(QPArgs a) {
   extern __shared__ double sm[];
   __shared__ double red[QT / 64];
@@ -328,67 +358,92 @@ __global__ __launch_bounds__(QT) void k_qp_dir(QPArgs a) {
       us[c] = j < N ? a.u[D.ou + (int64_t)j * nu + c] : 0.0;
       dus[c] = j < N ? a.du[D.ou + (int64_t)j * nu + c] : 0.0;
     }
-    __syncthreads();
+    // stage matrices (null where the stage has none; the staged copies are read only where the
+    // global ones are not null)
     const double* Cj = a.C + (int64_t)m * D.oq + (int64_t)j * m * nx;
     const double* Dj = j < N ? a.D + (int64_t)m * D.or_ + (int64_t)j * m * nu : nullptr;
+    const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
+    const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
+    const double* Rj = j < N ? a.d.R + D.oR + (int64_t)j * nu * nu : nullptr;
+    const double* Aj = j < N ? a.d.A + D.oA + (int64_t)j * nx * nx : nullptr;
+    const double* Bj = j < N ? a.d.B + D.oB + (int64_t)j * nx * nu : nullptr;
+    const double *Cs = Cj, *Ds = Dj, *Qs = Qj, *Ss = Sj, *Rs = Rj, *As = Aj, *Bs = Bj;
+    if constexpr (STG) {
+      double* p = sm + a.omats;
+      stage_copy(p, Cj, m * nx);
+      Cs = p;
+      p += m * nx;
+      if (Dj) stage_copy(p, Dj, m * nu);
+      Ds = p;
+      p += m * nu;
+      if (j >= 1) stage_copy(p, Qj, nx * nx);
+      Qs = p;
+      p += nx * nx;
+      if (Sj) stage_copy(p, Sj, nu * nx);
+      Ss = p;
+      p += nu * nx;
+      if (Rj) stage_copy(p, Rj, nu * nu);
+      Rs = p;
+      p += nu * nu;
+      if (Aj && j >= 1) stage_copy(p, Aj, nx * nx);
+      As = p;
+      p += nx * nx;
+      if (Bj) stage_copy(p, Bj, nx * nu);
+      Bs = p;
+    }
+    __syncthreads();
     const int64_t rj = (int64_t)m * D.oK + (int64_t)j * m;
     double dm = 0.0;
     for (int i = tid; i < m; i += QT) {
       double g = 0.0;
-      for (int c = 0; c < nx; ++c) g += Cj[(int64_t)i * nx + c] * dxs[c];
+      for (int c = 0; c < nx; ++c) g += Cs[(int64_t)i * nx + c] * dxs[c];
       if (Dj)
-        for (int c = 0; c < nu; ++c) g += Dj[(int64_t)i * nu + c] * dus[c];
+        for (int c = 0; c < nu; ++c) g += Ds[(int64_t)i * nu + c] * dus[c];
       a.gd[rj + i] = g;
     }
-    const double* Qj = a.d.Q + D.oQ + (int64_t)j * nx * nx;
-    const double* Sj = j < N && a.d.S ? a.d.S + D.oS + (int64_t)j * nu * nx : nullptr;
     const double* xbj = j >= 1 ? a.xbar + D.ox + (int64_t)(j - 1) * nx : nullptr;
     double eta = 0.0, beta = 0.0, rin = 0.0;
     if (j >= 1)
       for (int p = tid; p < nx; p += QT) {
         double hx = 0.0, gx = a.d.q[D.oq + (int64_t)j * nx + p];
         for (int q = 0; q < nx; ++q) {
-          const double qs = 0.5 * (Qj[p * nx + q] + Qj[q * nx + p]);
+          const double qs = 0.5 * (Qs[p * nx + q] + Qs[q * nx + p]);
           hx += qs * dxs[q];
           gx += qs * xs[q];
         }
         if (Sj)
           for (int c = 0; c < nu; ++c) {
-            hx += Sj[(int64_t)c * nx + p] * dus[c];  // with the u part below: 2 du^T S dx in all
-            gx += Sj[(int64_t)c * nx + p] * us[c];
+            hx += Ss[(int64_t)c * nx + p] * dus[c];  // with the u part below: 2 du^T S dx in all
+            gx += Ss[(int64_t)c * nx + p] * us[c];
           }
         eta += dxs[p] * hx + a.ginv * dxs[p] * dxs[p];
         beta += dxs[p] * (gx + a.ginv * (xs[p] - xbj[p]));
         dm = fmax(dm, fabs(dxs[p]));
         // inner residual of the x_j row: q_j + A_j^T lam_j - lam_{j-1}
         double r = a.qn[D.oq + (int64_t)j * nx + p] - a.dlam[D.olam + (int64_t)(j - 1) * nx + p];
-        if (j < N) {
-          const double* Aj = a.d.A + D.oA + (int64_t)j * nx * nx;
-          for (int q = 0; q < nx; ++q) r += Aj[(int64_t)q * nx + p] * a.dlam[D.olam + (int64_t)j * nx + q];
-        }
+        if (j < N)
+          for (int q = 0; q < nx; ++q) r += As[(int64_t)q * nx + p] * a.dlam[D.olam + (int64_t)j * nx + q];
         rin = fmax(rin, fabs(r));
       }
     if (j < N) {
-      const double* Rj = a.d.R + D.oR + (int64_t)j * nu * nu;
-      const double* Bj = a.d.B + D.oB + (int64_t)j * nx * nu;
       const double* ubj = a.ubar + D.ou + (int64_t)j * nu;
       for (int c = tid; c < nu; c += QT) {
         double hu = 0.0, gu = a.d.r[D.or_ + (int64_t)j * nu + c];
         for (int q = 0; q < nu; ++q) {
-          const double rs = 0.5 * (Rj[c * nu + q] + Rj[q * nu + c]);
+          const double rs = 0.5 * (Rs[c * nu + q] + Rs[q * nu + c]);
           hu += rs * dus[q];
           gu += rs * us[q];
         }
         if (Sj)
           for (int q = 0; q < nx; ++q) {
-            hu += Sj[(int64_t)c * nx + q] * dxs[q];
-            gu += Sj[(int64_t)c * nx + q] * xs[q];
+            hu += Ss[(int64_t)c * nx + q] * dxs[q];
+            gu += Ss[(int64_t)c * nx + q] * xs[q];
           }
         eta += dus[c] * hu + a.ginv * dus[c] * dus[c];
         beta += dus[c] * (gu + a.ginv * (us[c] - ubj[c]));
         dm = fmax(dm, fabs(dus[c]));
         double r = a.rn[D.or_ + (int64_t)j * nu + c];
-        for (int q = 0; q < nx; ++q) r += Bj[(int64_t)q * nu + c] * a.dlam[D.olam + (int64_t)j * nx + q];
+        for (int q = 0; q < nx; ++q) r += Bs[(int64_t)q * nu + c] * a.dlam[D.olam + (int64_t)j * nx + q];
         rin = fmax(rin, fabs(r));
       }
     }
@@ -878,10 +933,25 @@ hipError_t qp_refine(int which, const QPArgs& a, int maxN, int nxmax, int numax,
   return hipGetLastError();
 }
 
-hipError_t qp_launch(int which, const QPArgs& a, int maxN, int nxmax, int numax, hipStream_t st, const int32_t* info,
+// Doubles of one stage's matrices staged by k_qp_newton / k_qp_dir: C, D, Q, S, R, A, B.
+static size_t qp_mats_doubles(int nxmax, int numax, int m) {
+  const size_t x = nxmax, u = numax;
+  return (size_t)m * (x + u) + 2 * x * x + 2 * x * u + u * u;
+}
+
+hipError_t qp_launch(int which, const QPArgs& a0, int maxN, int nxmax, int numax, hipStream_t st, const int32_t* info,
                      int32_t* out) {
-  const size_t lds = qp_stage_lds(nxmax, numax, a.m);
-  const dim3 sgrid((maxN + 1 + QSG - 1) / QSG, a.batch);
+  const size_t base = qp_stage_lds(nxmax, numax, a0.m);
+  const dim3 sgrid((maxN + 1 + QSG - 1) / QSG, a0.batch);
+  // the stage-parallel kernels stage the stage matrices in LDS when the workgroup's LDS stays
+  // within 64 KiB (two or more workgroups per CU); larger shapes read them from global memory
+  const size_t staged = base + sizeof(double) * qp_mats_doubles(nxmax, numax, a0.m);
+  const bool stg = staged <= 65536;
+  QPArgs a = a0;
+  a.omats = (int64_t)(base / sizeof(double));
+  const size_t lds = base;
+  const void* kn = stg ? (const void*)k_qp_newton<true> : (const void*)k_qp_newton<false>;
+  const void* kd = stg ? (const void*)k_qp_dir<true> : (const void*)k_qp_dir<false>;
   hipError_t e;
   switch (which) {
     case 0:
@@ -889,13 +959,19 @@ hipError_t qp_launch(int which, const QPArgs& a, int maxN, int nxmax, int numax,
       hipLaunchKernelGGL(k_qp_init, dim3(a.batch), dim3(QT), lds, st, a);
       break;
     case 1:
-      if ((e = raise_lds_limit((const void*)k_qp_newton, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_qp_newton, sgrid, dim3(QT), lds, st, a);
+      if ((e = raise_lds_limit(kn, stg ? staged : lds)) != hipSuccess) return e;
+      {
+        void* args[] = {(void*)&a};
+        if ((e = hipLaunchKernel(kn, sgrid, dim3(QT), args, stg ? staged : lds, st)) != hipSuccess) return e;
+      }
       break;
     case 2:
       hipLaunchKernelGGL(k_qp_check_info, dim3((a.batch + 255) / 256), dim3(256), 0, st, a, info);
-      if ((e = raise_lds_limit((const void*)k_qp_dir, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_qp_dir, sgrid, dim3(QT), lds, st, a);
+      if ((e = raise_lds_limit(kd, stg ? staged : lds)) != hipSuccess) return e;
+      {
+        void* args[] = {(void*)&a};
+        if ((e = hipLaunchKernel(kd, sgrid, dim3(QT), args, stg ? staged : lds, st)) != hipSuccess) return e;
+      }
       hipLaunchKernelGGL(k_qp_search, dim3(a.batch), dim3(QT), 0, st, a);
       hipLaunchKernelGGL(k_qp_step, sgrid, dim3(QT), 0, st, a);
       if ((e = raise_lds_limit((const void*)k_qp_rollout, lds)) != hipSuccess) return e;

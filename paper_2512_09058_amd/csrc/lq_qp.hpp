@@ -22,6 +22,7 @@ struct QPArgs {
   int32_t* fl;                   // per instance: flags
   double sigma0, ginv, eps, theta, sigma_up, sigma_max, inner_tol;
   int32_t warm;
+  int64_t omats;  // stage-parallel kernels with staged stage matrices: their offset in dynamic LDS (doubles)
 };
 
 // Byte offsets of the QP workspace.

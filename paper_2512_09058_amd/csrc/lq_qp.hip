@@ -588,6 +588,28 @@ __device__ int local_breaks(const LineRows& L, double lo, double hi, int k, doub
   return c;
 }
 
+// Exclusive prefix sum of v over the workgroup (thread order), and its total: a shuffle scan in
+// each wavefront, then the wavefront totals through LDS.
+__device__ int block_excl_scan(int v, int* redi, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) redi[w] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < QT / 64; ++i) {
+    const int t = redi[i];
+    off += i < w ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  return off + x - v;
+}
+
 // Exact line search, one workgroup per instance: the inner-loop test first (stationarity residual,
 // a direction at rounding level), then the bisection over the breakpoints of psi' (a breakpoint in
 // the current bracket chosen as pivot: the median in index order; psi' at it decides the side), the
@@ -596,7 +618,6 @@ __device__ int local_breaks(const LineRows& L, double lo, double hi, int k, doub
 __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
   __shared__ double red[QT / 64];
   __shared__ int redi[QT / 64];
-  __shared__ int scnt[QT];
   __shared__ double s_piv;
   const int b = blockIdx.x, tid = threadIdx.x;
   int32_t* f = a.fl + (int64_t)b * FL_N;
@@ -643,21 +664,10 @@ __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
     for (int it = 0; it < 200 && !done; ++it) {
       double dummy = 0.0;
       const int c = local_breaks(L, lo, hi, -1, &dummy);
-      scnt[tid] = c;
-      __syncthreads();
-      if (tid == 0) {
-        int acc = 0;
-        for (int i = 0; i < QT; ++i) {
-          const int v = scnt[i];
-          scnt[i] = acc;
-          acc += v;
-        }
-        redi[0] = acc;
-      }
-      __syncthreads();
-      const int total = redi[0];
+      int total;
+      const int pre = block_excl_scan(c, redi, &total);
       if (total == 0) break;
-      const int rank = total / 2, pre = scnt[tid];
+      const int rank = total / 2;
       if (rank >= pre && rank < pre + c) {
         double t = 0.0;
         local_breaks(L, lo, hi, rank - pre, &t);

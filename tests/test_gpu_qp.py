@@ -96,6 +96,27 @@ def test_random_qps_with_S_f_and_one_sided_rows():
     _check(insts, Cs, Ds, bls, bus, _run(insts, Cs, Ds, bls, bus), "random")
 
 
+def test_wide_qps_with_stage_matrices_read_from_global_memory():
+    """nx = 60, nu = 10: a stage's matrices would take the stage-parallel kernels' workgroup past
+    64 KiB of LDS, so the Newton-system and direction kernels read them from global memory (the
+    other cases here run the instances that stage them in LDS)."""
+    print("case: wide QPs", flush=True)
+    insts, Cs, Ds, bls, bus = [], [], [], [], []
+    for s in range(2):
+        p = synth.random_problem(700 + s, 5, 60, 10)
+        rng = np.random.default_rng(700 + s)
+        p.A = 0.9 * np.linalg.qr(rng.standard_normal((5, 60, 60)))[0]
+        p.B = p.B / np.sqrt(60)
+        C = rng.standard_normal((6, 4, 60)) / np.sqrt(60)
+        D = rng.standard_normal((5, 4, 10)) / np.sqrt(10)
+        uf = rng.standard_normal((5, 10))
+        wf = oqp.constraint_values(p, C, D, oqp.rollout(p, uf), uf)
+        bl = wf - rng.uniform(0.05, 0.5, wf.shape)
+        bu = wf + rng.uniform(0.05, 0.5, wf.shape)
+        insts.append(p); Cs.append(C); Ds.append(D); bls.append(bl); bus.append(bu)
+    _check(insts, Cs, Ds, bls, bus, _run(insts, Cs, Ds, bls, bus), "wide")
+
+
 def test_warm_start_from_the_solution():
     print("case: warm start", flush=True)
     prob, C, D, bl, bu = synth.mass_spring(6, 12, 2, seed=9)

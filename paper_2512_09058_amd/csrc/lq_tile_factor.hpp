@@ -584,6 +584,9 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
     const int j0 = k == N ? TU : 0, j1 = k == 0 ? TU : T;
     for (int j = j0; j < j1; ++j) {
       if (own && a == j) {
+        // the diagonal step is the stage's critical path: its wavefront goes first among the
+        // wavefronts that share its SIMD (this workgroup's and co-resident ones) until it is done
+        __builtin_amdgcn_s_setprio(3);
         // lane coordinates re-derived here so that the diagonal step's per-lane addresses and
         // masks are not kept live across the whole pivot loop
         int dt = tid;
@@ -635,6 +638,7 @@ __device__ __forceinline__ void factor_tile_range(const Desc& D, const lq_data& 
         // the diagonal step reuse their registers
 #pragma unroll
         for (int bb = 0; bb < TMAX; ++bb) G[bb] = d4{0, 0, 0, 0};
+        __builtin_amdgcn_s_setprio(0);
       }
       __syncthreads();
       d4 Uf = d4{0, 0, 0, 0};

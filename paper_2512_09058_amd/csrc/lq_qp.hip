@@ -60,6 +60,28 @@ __device__ int block_sum_i(int v, int* redi) {
   return s;
 }
 
+// Exclusive prefix sum of v over the workgroup (thread order), and its total: a shuffle scan in
+// each wavefront, then the wavefront totals through LDS.
+__device__ int block_excl_scan(int v, int* redi, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) redi[w] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < QT / 64; ++i) {
+    const int t = redi[i];
+    off += i < w ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  return off + x - v;
+}
+
 // x_{k+1} = A_k x_k + B_k u_k + f_k from x_init, the whole workgroup on one instance.
 __device__ void rollout(const QPArgs& a, const Desc& D, double* xs) {
   const int N = D.N, nx = D.nx, nu = D.nu, tid = threadIdx.x;
@@ -204,7 +226,7 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
   double* yh = us + nu;
   double* ss = yh + m;
   __shared__ int s_act[256];  // active rows of the stage (the only ones with Sigma^J and yhat nonzero)
-  __shared__ int s_na;
+  __shared__ int redi[QT / 64];
   for (int j = blockIdx.x * QSG; j < blockIdx.x * QSG + QSG && j <= N; ++j) {
     const double* xj = j == 0 ? a.d.x0 + D.ox0 : a.x + D.ox + (int64_t)(j - 1) * nx;
     for (int i = tid; i < nx; i += QT) xs[i] = xj[i];
@@ -256,15 +278,15 @@ __global__ __launch_bounds__(QT) void k_qp_newton(QPArgs a) {
     for (int c = tid; c < nu; c += QT) sc = fmax(sc, fabs(us[c]));
     __syncthreads();
     sc = block_max(sc, red);
-    if (tid == 0) {
-      a.part[(D.oK + j) * NP + 4] = sc;
-      int na = 0;
-      for (int i = 0; i < m; ++i)
-        if (ss[i] != 0.0) s_act[na++] = i;
-      s_na = na;
+    if (tid == 0) a.part[(D.oK + j) * NP + 4] = sc;
+    // active rows in increasing order (m <= QT: one row per thread), compacted by a prefix sum
+    int na;
+    {
+      const bool on = tid < m && ss[tid] != 0.0;
+      const int pos = block_excl_scan(on ? 1 : 0, redi, &na);
+      if (on) s_act[pos] = tid;
     }
     __syncthreads();
-    const int na = s_na;
     // Hessian blocks
     double* Qnj = a.Qn + D.oQ + (int64_t)j * nx * nx;
     for (int e = tid; e < nx * nx; e += QT) {
@@ -586,28 +608,6 @@ __device__ int local_breaks(const LineRows& L, double lo, double hi, int k, doub
     }
   }
   return c;
-}
-
-// Exclusive prefix sum of v over the workgroup (thread order), and its total: a shuffle scan in
-// each wavefront, then the wavefront totals through LDS.
-__device__ int block_excl_scan(int v, int* redi, int* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  __syncthreads();
-  if (lane == 63) redi[w] = x;
-  __syncthreads();
-  int off = 0, tot = 0;
-  for (int i = 0; i < QT / 64; ++i) {
-    const int t = redi[i];
-    off += i < w ? t : 0;
-    tot += t;
-  }
-  *total = tot;
-  return off + x - v;
 }
 
 // Exact line search, one workgroup per instance: the inner-loop test first (stationarity residual,

@@ -82,8 +82,86 @@ __device__ int block_excl_scan(int v, int* redi, int* total) {
   return off + x - v;
 }
 
-// x_{k+1} = A_k x_k + B_k u_k + f_k from x_init, the whole workgroup on one instance.
+constexpr int RPT = 4;  // staged rollout: elements per thread and stage (two LDS slots of RPT QT)
+
+// Elements of one stage staged by rollout_staged: [A_k B_k] row-major (nx rows of nx + nu), u_k,
+// and f_k when the problem has f.
+__host__ __device__ inline int roll_elems(int nx, int nu, bool hf) { return nx * (nx + nu) + nu + (hf ? nx : 0); }
+
+// rollout with every stage's [A_k B_k], u_k, f_k copied into LDS one stage ahead, in two slots:
+// the loads of stage k + 1 are issued before stage k's products and stored into the other slot
+// after them, so that a stage waits for what is left of one round trip at most, and the products
+// read LDS only.  The same terms in the same order as the loop of rollout below.
+__device__ void rollout_staged(const QPArgs& a, const Desc& D, double* xs, double* buf) {
+  const int N = D.N, nx = D.nx, nu = D.nu, tid = threadIdx.x, w = nx + nu;
+  const bool hf = a.d.f != nullptr;
+  const int ne = roll_elems(nx, nu, hf), nab = nx * w;
+  const double* A = a.d.A + D.oA;
+  const double* B = a.d.B + D.oB;
+  const double* U = a.u + D.ou;
+  const double* F = hf ? a.d.f + D.of : A;  // (no f element is staged without f)
+  // this thread's elements: array (0 A, 1 B, 2 u, 3 f) and offset within a stage; past the last
+  // element the last one is loaded again and not stored
+  int kind[RPT], off[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int e = min(tid + q * QT, ne - 1);
+    if (e < nab) {
+      const int r = e / w, c = e - r * w;
+      kind[q] = c < nx ? 0 : 1;
+      off[q] = c < nx ? r * nx + c : r * nu + (c - nx);
+    } else if (e < nab + nu) {
+      kind[q] = 2;
+      off[q] = e - nab;
+    } else {
+      kind[q] = 3;
+      off[q] = e - nab - nu;
+    }
+  }
+  auto src = [&](int k, int q) -> const double* {
+    const int64_t kk = min(k, N - 1);
+    return kind[q] == 0 ? A + kk * nx * nx + off[q]
+         : kind[q] == 1 ? B + kk * nx * nu + off[q]
+         : kind[q] == 2 ? U + kk * nu + off[q]
+                        : F + kk * nx + off[q];
+  };
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+    if (tid + q * QT < ne) buf[tid + q * QT] = *src(0, q);
+  const double* x0 = a.d.x0 + D.ox0;
+  for (int i = tid; i < nx; i += QT) xs[i] = x0[i];
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    double v[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) v[q] = *src(k + 1, q);
+    const double* M = buf + (k & 1) * ne;
+    double s = 0.0;
+    if (tid < nx) {
+      s = hf ? M[nab + nu + tid] : 0.0;
+      for (int c = 0; c < nx; ++c) s += M[tid * w + c] * xs[c];
+      for (int c = 0; c < nu; ++c) s += M[tid * w + nx + c] * M[nab + c];
+    }
+    __syncthreads();
+    if (tid < nx) {
+      xs[tid] = s;
+      a.x[D.ox + (int64_t)k * nx + tid] = s;
+    }
+    double* Mn = buf + ((k + 1) & 1) * ne;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (tid + q * QT < ne) Mn[tid + q * QT] = v[q];
+    __syncthreads();
+  }
+}
+
+// x_{k+1} = A_k x_k + B_k u_k + f_k from x_init, the whole workgroup on one instance (staged
+// through LDS where the launch gave the slots and a stage fits them).
 __device__ void rollout(const QPArgs& a, const Desc& D, double* xs) {
+  if (a.orbuf > 0 && roll_elems(D.nx, D.nu, a.d.f != nullptr) <= RPT * QT) {
+    rollout_staged(a, D, xs, xs + a.orbuf);
+    return;
+  }
   const int N = D.N, nx = D.nx, nu = D.nu, tid = threadIdx.x;
   const double* x0 = a.d.x0 + D.ox0;
   for (int i = tid; i < nx; i += QT) xs[i] = x0[i];
@@ -960,13 +1038,19 @@ hipError_t qp_launch(int which, const QPArgs& a0, int maxN, int nxmax, int numax
   QPArgs a = a0;
   a.omats = (int64_t)(base / sizeof(double));
   const size_t lds = base;
+  // rollouts (k_qp_init, k_qp_rollout, k_qp_outer_fin): two LDS slots of RPT QT doubles after the
+  // base region, where that stays within 64 KiB
+  const size_t rslots = 2 * sizeof(double) * (size_t)RPT * QT;
+  const bool rst = base + rslots <= 65536;
+  a.orbuf = rst ? (int64_t)(base / sizeof(double)) : 0;
+  const size_t lds_r = rst ? base + rslots : base;
   const void* kn = stg ? (const void*)k_qp_newton<true> : (const void*)k_qp_newton<false>;
   const void* kd = stg ? (const void*)k_qp_dir<true> : (const void*)k_qp_dir<false>;
   hipError_t e;
   switch (which) {
     case 0:
-      if ((e = raise_lds_limit((const void*)k_qp_init, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_qp_init, dim3(a.batch), dim3(QT), lds, st, a);
+      if ((e = raise_lds_limit((const void*)k_qp_init, lds_r)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_init, dim3(a.batch), dim3(QT), lds_r, st, a);
       break;
     case 1:
       if ((e = raise_lds_limit(kn, stg ? staged : lds)) != hipSuccess) return e;
@@ -984,15 +1068,15 @@ hipError_t qp_launch(int which, const QPArgs& a0, int maxN, int nxmax, int numax
       }
       hipLaunchKernelGGL(k_qp_search, dim3(a.batch), dim3(QT), 0, st, a);
       hipLaunchKernelGGL(k_qp_step, sgrid, dim3(QT), 0, st, a);
-      if ((e = raise_lds_limit((const void*)k_qp_rollout, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_qp_rollout, dim3(a.batch), dim3(QT), lds, st, a);
+      if ((e = raise_lds_limit((const void*)k_qp_rollout, lds_r)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_qp_rollout, dim3(a.batch), dim3(QT), lds_r, st, a);
       hipLaunchKernelGGL(k_qp_count, dim3(1), dim3(QT), 0, st, a, 0, out);
       break;
     case 3:
       if ((e = raise_lds_limit((const void*)k_qp_outer, lds)) != hipSuccess) return e;
-      if ((e = raise_lds_limit((const void*)k_qp_outer_fin, lds)) != hipSuccess) return e;
+      if ((e = raise_lds_limit((const void*)k_qp_outer_fin, lds_r)) != hipSuccess) return e;
       hipLaunchKernelGGL(k_qp_outer, sgrid, dim3(QT), lds, st, a);
-      hipLaunchKernelGGL(k_qp_outer_fin, dim3(a.batch), dim3(QT), lds, st, a);
+      hipLaunchKernelGGL(k_qp_outer_fin, dim3(a.batch), dim3(QT), lds_r, st, a);
       hipLaunchKernelGGL(k_qp_outer_upd, sgrid, dim3(QT), 0, st, a);
       hipLaunchKernelGGL(k_qp_count, dim3(1), dim3(QT), 0, st, a, 1, out);
       break;

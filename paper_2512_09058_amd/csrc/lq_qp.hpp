@@ -23,6 +23,7 @@ struct QPArgs {
   double sigma0, ginv, eps, theta, sigma_up, sigma_max, inner_tol;
   int32_t warm;
   int64_t omats;  // stage-parallel kernels with staged stage matrices: their offset in dynamic LDS (doubles)
+  int64_t orbuf;  // rollouts with staged stages: offset of their two LDS slots (doubles; 0: none)
 };
 
 // Byte offsets of the QP workspace.

@@ -688,6 +688,60 @@ __device__ int local_breaks(const LineRows& L, double lo, double hi, int k, doub
   return c;
 }
 
+// The row terms of one thread's chunk (at most RC rows), computed once per line search and kept
+// in registers: slope and breakpoint passes then read no global memory.  Same terms, same order as
+// slope_at / local_breaks (which the search uses for longer chunks).
+constexpr int RC = 12;
+struct RowCache {
+  double d0[RC], a0[RC], d1[RC], a1[RC];
+  bool h0[RC], h1[RC];
+  int n;  // rows of this thread
+};
+
+__device__ __forceinline__ void row_cache_fill(const LineRows& L, RowCache& C) {
+  const int64_t r0 = threadIdx.x * L.chunk, r1 = min(L.R, r0 + L.chunk);
+  C.n = (int)max((int64_t)0, r1 - r0);
+  // every slot is filled (rows past the chunk repeat a row of the instance and are never read),
+  // so that the slots stay in registers
+#pragma unroll
+  for (int q = 0; q < RC; ++q) {
+    const int64_t r = min(r0 + min(q, max(C.n - 1, 0)), L.R - 1);
+    row_terms(L, r, C.d0[q], C.a0[q], C.d1[q], C.a1[q], C.h0[q], C.h1[q]);
+  }
+}
+
+__device__ __forceinline__ double slope_cached(const RowCache& C, double eta, double beta, double t, double* red) {
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) {
+    if (q < C.n && C.h0[q]) acc += C.d0[q] * fmax(C.d0[q] * t - C.a0[q], 0.0);
+    if (q < C.n && C.h1[q]) acc += C.d1[q] * fmax(C.d1[q] * t - C.a1[q], 0.0);
+  }
+  return eta * t + beta + block_sum(acc, red);
+}
+
+__device__ __forceinline__ int breaks_cached(const RowCache& C, double lo, double hi, int k, double* kth) {
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < RC; ++q) {
+    if (q < C.n && C.h0[q] && C.d0[q] != 0.0) {
+      const double t = C.a0[q] / C.d0[q];
+      if (t > lo && t < hi) {
+        if (c == k) *kth = t;
+        ++c;
+      }
+    }
+    if (q < C.n && C.h1[q] && C.d1[q] != 0.0) {
+      const double t = C.a1[q] / C.d1[q];
+      if (t > lo && t < hi) {
+        if (c == k) *kth = t;
+        ++c;
+      }
+    }
+  }
+  return c;
+}
+
 // Exact line search, one workgroup per instance: the inner-loop test first (stationarity residual,
 // a direction at rounding level), then the bisection over the breakpoints of psi' (a breakpoint in
 // the current bracket chosen as pivot: the median in index order; psi' at it decides the side), the
@@ -731,8 +785,16 @@ __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
   L.w = a.w + o; L.gd = a.gd + o; L.y = a.y + o; L.sig = a.sig + o; L.bl = a.bl + o; L.bu = a.bu + o;
   L.R = (int64_t)a.m * (N + 1);
   L.chunk = (L.R + QT - 1) / QT;
+  const bool cached = L.chunk <= RC;  // (uniform)
+  RowCache C;
+  C.n = 0;
+  if (cached) row_cache_fill(L, C);
+  auto slope = [&](double t) { return cached ? slope_cached(C, eta, beta, t, red) : slope_at(L, eta, beta, t, red); };
+  auto breaks = [&](double lo_, double hi_, int k, double* kth) {
+    return cached ? breaks_cached(C, lo_, hi_, k, kth) : local_breaks(L, lo_, hi_, k, kth);
+  };
   double tau;
-  const double s0 = slope_at(L, eta, beta, 0.0, red);
+  const double s0 = slope(0.0);
   if (!(s0 < 0.0)) {
     tau = 1.0;  // the decrease is below the rounding of psi': take the full Newton step
   } else {
@@ -741,19 +803,19 @@ __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
     tau = 0.0;
     for (int it = 0; it < 200 && !done; ++it) {
       double dummy = 0.0;
-      const int c = local_breaks(L, lo, hi, -1, &dummy);
+      const int c = breaks(lo, hi, -1, &dummy);
       int total;
       const int pre = block_excl_scan(c, redi, &total);
       if (total == 0) break;
       const int rank = total / 2;
       if (rank >= pre && rank < pre + c) {
         double t = 0.0;
-        local_breaks(L, lo, hi, rank - pre, &t);
+        breaks(lo, hi, rank - pre, &t);
         s_piv = t;
       }
       __syncthreads();
       const double tp = s_piv;
-      const double sp = slope_at(L, eta, beta, tp, red);
+      const double sp = slope(tp);
       if (sp == 0.0) {
         tau = tp;
         done = true;
@@ -767,7 +829,7 @@ __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
       // psi' is linear on (lo, hi): its root from two interior points
       const double t0 = hi < INFINITY ? lo + 0.25 * (hi - lo) : lo + 1.0;
       const double t1 = hi < INFINITY ? lo + 0.75 * (hi - lo) : lo + 2.0;
-      const double f0 = slope_at(L, eta, beta, t0, red), f1 = slope_at(L, eta, beta, t1, red);
+      const double f0 = slope(t0), f1 = slope(t1);
       tau = t0 - f0 * (t1 - t0) / (f1 - f0);
       tau = fmin(fmax(tau, lo), hi);
     }
@@ -776,7 +838,7 @@ __global__ __launch_bounds__(QT) void k_qp_search(QPArgs a) {
   int exact = 0;
   if (fabs(tau - 1.0) <= 1e-8) {
     double dummy = 0.0;
-    const int c = local_breaks(L, 0.0, tau, -1, &dummy);
+    const int c = breaks(0.0, tau, -1, &dummy);
     exact = block_sum_i(c, redi) == 0;
   }
   if (tid == 0) {
